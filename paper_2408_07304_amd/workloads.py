@@ -1,0 +1,150 @@
+"""Seeded synthetic workloads (parameter sets and input generators).
+
+This module holds no arithmetic of the encryption method: only the parameter
+sets of the benchmark configurations and seeded generators of the plaintext
+slot vectors, ciphertext identifiers, mixed-batch item lists and serving
+arrival traces.  Both the GPU path and the CPU oracle are fed from here.
+
+The paper's own evaluation datasets (U.S. Covid-19 statistics, Bitcoin trade
+volume, the hg38 table; Experimental Setup section) are not available; the
+synthetic inputs below stand in for them.  Values are uniform on [-1, 1) or a
+clipped standard normal, the distributions of the benchmark configurations.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass(frozen=True)
+class ParamSet:
+    name: str
+    log_n: int
+    bits: tuple            # moduli bit sizes; the last modulus is the special prime
+    scale: float           # Delta
+    seed: int = 0          # scheme randomness seed (Philox key)
+
+    @property
+    def n(self) -> int:
+        return 1 << self.log_n
+
+    @property
+    def slots(self) -> int:
+        return self.n // 2
+
+    @property
+    def n_moduli(self) -> int:
+        return len(self.bits)
+
+    @property
+    def limbs(self) -> int:
+        return len(self.bits) - 1
+
+
+# N = 4096: two 30-bit data primes plus one 30-bit special prime, Delta = 2^25.
+P4096 = ParamSet("n4096", 12, (30, 30, 30), 2.0 ** 25)
+# N = 8192: [60, 40, 40 | 60], Delta = 2^40.
+P8192 = ParamSet("n8192", 13, (60, 40, 40, 60), 2.0 ** 40)
+# N = 16384: [60, 50 x 6 | 60], Delta = 2^50.
+P16384 = ParamSet("n16384", 14, (60, 50, 50, 50, 50, 50, 50, 60), 2.0 ** 50)
+# N = 32768: 15 x 55-bit primes (14 data limbs + special), Delta = 2^55
+# (the paper's ring degree and scale; System Implementation section).
+P32768 = ParamSet("n32768", 15, (55,) * 15, 2.0 ** 55)
+
+PARAM_SETS = {p.name: p for p in (P4096, P8192, P16384, P32768)}
+
+
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    params: tuple          # one ParamSet, or several for the mixed batch
+    batch: int
+    dist: str              # "uniform" on [-1,1) or "gauss_clip8"
+    data_seed: int
+
+
+W_SMALL = Workload("n4096_b64", (P4096,), 64, "uniform", 0)
+W_MAIN = Workload("n8192_b1024", (P8192,), 1024, "uniform", 2)
+W_LARGE = Workload("n16384_b4096", (P16384,), 4096, "gauss_clip8", 3)
+W_MIXED = Workload("mixed_b2048", (P4096, P8192, P16384, P32768), 2048, "uniform", 4)
+WORKLOADS = {w.name: w for w in (W_SMALL, W_MAIN, W_LARGE, W_MIXED)}
+
+
+def slot_values(rng: np.random.Generator, count: int, n_slots: int, dist: str) -> np.ndarray:
+    if dist == "uniform":
+        return rng.uniform(-1.0, 1.0, size=(count, n_slots))
+    if dist == "gauss_clip8":
+        return np.clip(rng.standard_normal(size=(count, n_slots)), -8.0, 8.0)
+    raise ValueError(dist)
+
+
+def make_slots(w: Workload, count: int | None = None, params: ParamSet | None = None) -> np.ndarray:
+    """float64 [count][N/2] slot vectors of a single-parameter workload."""
+    p = params or w.params[0]
+    rng = np.random.default_rng(w.data_seed)
+    return slot_values(rng, w.batch if count is None else count, p.slots, w.dist)
+
+
+def make_ct_ids(count: int, first: int = 0) -> np.ndarray:
+    return np.arange(first, first + count, dtype=np.uint64)
+
+
+@dataclass
+class MixedBatch:
+    """Items of a mixed batch: per item its parameter-set index, slot offset
+    (in float64 elements), ciphertext offset (in uint64 words) and ct_id."""
+    params: tuple
+    ctx_idx: np.ndarray
+    slot_off: np.ndarray
+    ct_off: np.ndarray
+    ct_id: np.ndarray
+    slots: np.ndarray          # flat float64
+    ct_words: int
+
+
+def make_mixed(w: Workload = W_MIXED, count: int | None = None) -> MixedBatch:
+    """Mixed batch: each plaintext draws its parameter set uniformly from
+    w.params; slots are uniform on [-1, 1) (N/2 of them)."""
+    rng = np.random.default_rng(w.data_seed)
+    b = w.batch if count is None else count
+    idx = rng.integers(0, len(w.params), size=b)
+    slot_off = np.zeros(b, dtype=np.uint64)
+    ct_off = np.zeros(b, dtype=np.uint64)
+    chunks = []
+    so = co = 0
+    for i in range(b):
+        p = w.params[int(idx[i])]
+        slot_off[i] = so
+        ct_off[i] = co
+        chunks.append(slot_values(rng, 1, p.slots, w.dist)[0])
+        so += p.slots
+        co += 2 * p.limbs * p.n
+    return MixedBatch(w.params, idx.astype(np.uint32), slot_off, ct_off,
+                      np.arange(b, dtype=np.uint64), np.concatenate(chunks), co)
+
+
+@dataclass
+class Request:
+    arrival: float         # seconds from trace start
+    param: int             # index into the parameter-set tuple
+    count: int             # plaintexts in the request
+    rid: int
+    slots: np.ndarray = field(repr=False, default=None)
+
+
+def make_trace(n_requests: int, rate_per_s: float, params: tuple = W_MIXED.params,
+               seed: int = 5, max_count: int = 64, with_slots: bool = True) -> list:
+    """Open-loop Poisson arrival trace: exponential inter-arrival times at
+    rate_per_s, request size uniform on {1..max_count}, parameter set uniform
+    over `params`, slots uniform on [-1, 1)."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for r in range(n_requests):
+        t += rng.exponential(1.0 / rate_per_s)
+        pi = int(rng.integers(0, len(params)))
+        cnt = int(rng.integers(1, max_count + 1))
+        s = slot_values(rng, cnt, params[pi].slots, "uniform") if with_slots else None
+        out.append(Request(t, pi, cnt, r, s))
+    return out

@@ -1,0 +1,202 @@
+"""Throughput benchmark: batched CKKS encryption on one MI355X, Zinc
+(Algorithm 1) against vanilla public-key encryption (Eq. 8) on the same GPU.
+
+One step = one fused launch (FP64 encode + sampling + every limb's NTTs + the
+cached-Enc(0) / pk*u epilogue) over the whole batch of the workload, inputs
+resident in HBM.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload n8192_b1024]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "CKKS encryptions/sec (Zinc vs vanilla, same GPU) at N=8192; p99 latency served"
+
+# ALU roofline of the NTT butterfly (the dominant work of the fused launch).
+# VALU issue rate of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.32e12
+# lane-cycles/s.  A 64-bit Shoup butterfly needs at least 10 multiply-class
+# instructions (hi(y*w') from four 32x32 partial products, two low 64-bit
+# products from three each), issued at a quarter of the full rate, plus 12
+# full-rate adds, compares and selects: 52 lane-cycles.
+VALU_LANE_CYCLES_PER_S = 256 * 4 * 16 * 2.4e9
+BFLY_LANE_CYCLES = 10 * 4 + 12
+PEAK_BFLY_PER_S = VALU_LANE_CYCLES_PER_S / BFLY_LANE_CYCLES
+HBM_PEAK_BYTES_PER_S = 8.0e12
+KERNEL_SOURCES = ("paper_2408_07304_amd/csrc/kernels.hip", "paper_2408_07304_amd/csrc/device.h")
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def butterflies(n: int, limbs: int, scheme: int) -> int:
+    ntts = (2 if scheme == 1 else 3) * limbs
+    return ntts * (n // 2) * int(math.log2(n))
+
+
+def algorithmic_bytes(n: int, limbs: int, n_slots: int) -> int:
+    """HBM bytes one encryption must move: slots in, ciphertext out."""
+    return 8 * n_slots + 16 * limbs * n
+
+
+def traffic_from_profile(workload: str, scheme_name: str):
+    """Measured HBM bytes per launch from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"traffic_encrypt_{scheme_name}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("kernel_hash") != kernel_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(ws, scheme: int, budget_s: float):
+    """The CPU oracle (plain C, -O2, scalar) on a bounded sample of the same
+    workload: encode + encrypt of the first plaintexts, one per thread."""
+    import concurrent.futures as cf
+
+    import numpy as np
+
+    import oracle
+    from paper_2408_07304_amd.workloads import make_slots
+
+    ps = ws.params[0]
+    P = oracle.Params(ps.log_n, ps.bits, ps.scale, ps.seed)
+    _, pk = oracle.keygen(P)
+    key = oracle.zinc_precompute(P, pk) if scheme == 1 else pk
+    threads = max(1, min(os.cpu_count() or 1, 16))
+    z = make_slots(ws, min(ws.batch, 4 * threads))
+    t0 = time.perf_counter()
+    oracle.encrypt_slots(P, scheme, key, z[0], 0)
+    one = time.perf_counter() - t0
+    count = int(max(threads, min(len(z), threads * max(1, budget_s / max(one, 1e-6)))))
+    count = min(count, len(z))
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(lambda i: oracle.encrypt_slots(P, scheme, key, z[i], i), range(count)))
+    dt = time.perf_counter() - t0
+    return {"value": count / dt, "unit": "enc/s", "cores": threads, "kind": "oracle",
+            "sample": f"{count} of {ws.batch} plaintexts of {ws.name} (encode + "
+                      f"{'Zinc' if scheme == 1 else 'vanilla'} encrypt), {threads} threads, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="n8192_b1024")
+    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--scheme", choices=["both", "zinc", "vanilla"], default="both")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}); "
+              "ciphertexts are independent, so N GPUs would each run this benchmark on 1/N of the batch.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2408_07304_amd as zinc
+    from paper_2408_07304_amd.workloads import WORKLOADS, make_slots
+
+    ws = WORKLOADS[args.workload]
+    if len(ws.params) != 1:
+        raise SystemExit("the throughput benchmark runs single-parameter workloads")
+    ps = ws.params[0]
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    ctx = zinc.context_for(ps)
+    ctx.keygen()
+    ctx.precompute()
+    z = torch.from_numpy(make_slots(ws)).to(dev)
+    ids = torch.arange(ws.batch, dtype=torch.int64, device=dev)
+    ct = torch.empty((ws.batch, 2, ps.limbs, ps.n), dtype=torch.int64, device=dev)
+    torch.cuda.synchronize()
+
+    schemes = {"zinc": 1, "vanilla": 0}
+    run = [s for s in ("zinc", "vanilla") if args.scheme in ("both", s)]
+    res = {}
+    for name in run:
+        sch = schemes[name]
+        for _ in range(args.warmup):
+            ctx.encrypt_slots(sch, z, ids, ct)
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+        t0 = time.perf_counter()
+        for a, b in ev:
+            a.record()
+            ctx.encrypt_slots(sch, z, ids, ct)
+            b.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        kms = [a.elapsed_time(b) for a, b in ev]
+        res[name] = {"ms_per_step": wall * 1e3 / args.steps, "kernel_ms": sum(kms) / len(kms),
+                     "kernel_ms_min": min(kms)}
+        print(f"[bench] {name}: {res[name]}", file=sys.stderr, flush=True)
+    if ctx.device_errors():
+        raise SystemExit("device error flag set during the benchmark")
+
+    main_name = run[0]
+    sch = schemes[main_name]
+    r = res[main_name]
+    value = ws.batch / (r["ms_per_step"] / 1e3)
+    bfly = ws.batch * butterflies(ps.n, ps.limbs, sch)
+    achieved = bfly / (r["kernel_ms"] / 1e3)
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "enc/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": ws.name, "N": ps.n, "moduli_bits": list(ps.bits), "data_limbs": ps.limbs,
+                   "scale_log2": int(math.log2(ps.scale)), "batch": ws.batch, "slots": ps.slots,
+                   "slot_values": ws.dist, "scheme": main_name, "fused_encode": True},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e9, "peak": PEAK_BFLY_PER_S / 1e9,
+                     "unit": "Gbutterfly/s", "frac": achieved / PEAK_BFLY_PER_S,
+                     "traffic": traffic_from_profile(ws.name, main_name),
+                     "kernel": "k_encrypt (fused encode + sample + NTT + add)",
+                     "kernel_ms": r["kernel_ms"], "butterflies_per_launch": bfly,
+                     "hbm_algorithmic_bytes_per_launch": ws.batch * algorithmic_bytes(ps.n, ps.limbs, ps.slots),
+                     "hbm_frac": ws.batch * algorithmic_bytes(ps.n, ps.limbs, ps.slots)
+                     / (r["kernel_ms"] / 1e3) / HBM_PEAK_BYTES_PER_S},
+    }
+    for name in run:
+        line[f"{name}_enc_per_s"] = ws.batch / (res[name]["ms_per_step"] / 1e3)
+        line[f"{name}_kernel_ms"] = res[name]["kernel_ms"]
+    if "vanilla" in res and "zinc" in res:
+        line["zinc_over_vanilla"] = res["vanilla"]["ms_per_step"] / res["zinc"]["ms_per_step"]
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(ws, sch, args.cpu_budget)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,236 @@
+/*
+ * zinc.h -- C ABI of the MI355X (gfx950) library for batched CKKS encryption:
+ * vanilla public-key encryption and Zinc encryption, from
+ * "At Least Factor-of-Two Optimization for RWLE-Based Homomorphic Encryption"
+ * (arXiv 2408.07304).
+ *
+ * The scheme follows the paper's statement of the problem: a homomorphic
+ * scheme Pi = (Gen, Enc, Dec, +, x) and its Zinc extension (Gen, Enc_z, Dec)
+ * (Security section).  Enc is Eq. 8 (vanilla CKKS encryption with the public
+ * key of Eq. 7), Enc_z is Algorithm 1 (cached Enc(0) plus the plaintext plus
+ * fresh Gaussian noise), Dec is [c1 + c2 sk]_q.  Encoding and decoding are the
+ * CKKS canonical embedding, which the paper takes from the CKKS paper.
+ *
+ * Data conventions (all sizes in elements):
+ *   N        ring degree, 2^log_n with 12 <= log_n <= 15.
+ *   M        moduli in the chain; the last one is the special prime, present in
+ *            the secret and public keys and absent from plaintexts and
+ *            ciphertexts.  L = M - 1 data limbs.
+ *   residues uint64, canonical in [0, q_l).
+ *   slots    double [batch][n_slots], n_slots <= N/2, real values; missing
+ *            slots up to N/2 are zero.
+ *   plaintext uint64 [batch][L][N], coefficient domain, limb-major.
+ *   ciphertext uint64 [batch][2][L][N] = (c1, c2), NTT domain, each limb in
+ *            bit-reversed evaluation order: c[k] = sum_i a_i psi^((2 brv(k)+1) i)
+ *            with psi the smallest primitive 2N-th root of unity mod q_l.
+ *   ct_ids   uint64 [batch]: every random coefficient of ciphertext b is a
+ *            function of (seed, ct_ids[b], tag, limb, index) only, so equal
+ *            identifiers give bit-identical ciphertexts in any batch, plan or
+ *            serving mix.  Identifiers must be < 2^63; ZINC_KEY_ID and
+ *            ZINC_ZERO_ID are reserved for the keys and the cached Enc(0).
+ *
+ * Memory ownership: pointers named d_* are device memory owned by the caller
+ * (contiguous, 8-byte aligned); the library never frees them and keeps no
+ * pointer to them after a call returns, except inside a plan (see
+ * zinc_plan_create).  The library owns its tables, keys and the Zinc cache.
+ *
+ * Streams: `stream` is a hipStream_t (NULL = the null stream).  Calls enqueue
+ * work and return; argument and state errors are reported synchronously.  A
+ * device fault surfaces at the caller's next synchronisation.  Range
+ * violations found on the device (a slot value whose scaled magnitude reaches
+ * 2^62, a decoded coefficient outside the limb-0 lift range) set a sticky flag
+ * read by zinc_device_errors.
+ *
+ * Threads: a context is read-only after zinc_precompute; encryption calls on
+ * one context may run concurrently on different streams.  zinc_keygen and
+ * zinc_precompute need exclusive use of the context.
+ *
+ * Every call returns a zinc_status; zinc_last_error() gives a message for the
+ * calling thread's most recent failure.
+ */
+#ifndef ZINC_H
+#define ZINC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int zinc_status;
+#define ZINC_OK 0
+#define ZINC_E_INVAL (-1)   /* null pointer, zero or oversized count, bad enum value   */
+#define ZINC_E_PARAM (-2)   /* invalid parameter set (ring degree, moduli, scale)      */
+#define ZINC_E_STATE (-3)   /* call out of order (encrypt before keygen/precompute)    */
+#define ZINC_E_NOMEM (-4)   /* device allocation failed                                */
+#define ZINC_E_HIP   (-5)   /* HIP runtime error (launch, copy, device)                */
+#define ZINC_E_RANGE (-6)   /* n_slots > N/2, scale too large for the moduli           */
+
+#define ZINC_KEY_ID  0xFFFFFFFFFFFFFFFFull
+#define ZINC_ZERO_ID 0xFFFFFFFFFFFFFFFEull
+#define ZINC_MAX_MODULI 32
+
+#define ZINC_SCHEME_VANILLA 0
+#define ZINC_SCHEME_ZINC    1
+
+/* Message describing the calling thread's last failed call ("" if none). */
+const char* zinc_last_error(void);
+
+typedef struct zinc_ctx zinc_ctx;
+typedef struct zinc_plan zinc_plan;
+
+/* Parameter set (Polynomials and Distributions; System Implementation).
+ *   log_n      ring degree N = 2^log_n, 12..15.
+ *   n_moduli   M, 2..ZINC_MAX_MODULI; the last modulus is the special prime.
+ *   bit_sizes  [M] bit sizes, 20..60, used when moduli == NULL: for each size,
+ *              in order, the largest prime q < 2^b with q = 1 mod 2N not
+ *              already chosen.
+ *   moduli     [M] explicit primes (each = 1 mod 2N, < 2^60, distinct) or NULL.
+ *   scale      Delta, > 0; Delta * 2^62 limits the slot magnitude.
+ *   sigma      standard deviation of chi; only 3.2 (the paper's value) is
+ *              accepted, as the sampler's cumulative table is built for it.
+ *   seed       64-bit key of the counter-based generator (Philox4x32-10). */
+typedef struct zinc_params {
+    uint32_t log_n;
+    uint32_t n_moduli;
+    const uint32_t* bit_sizes;
+    const uint64_t* moduli;
+    double scale;
+    double sigma;
+    uint64_t seed;
+} zinc_params;
+
+typedef struct zinc_info {
+    uint32_t n;                 /* N                                          */
+    uint32_t log_n;
+    uint32_t n_moduli;          /* M                                          */
+    uint32_t limbs;             /* L = M - 1                                  */
+    uint64_t moduli[ZINC_MAX_MODULI];
+    uint64_t psi[ZINC_MAX_MODULI];   /* smallest primitive 2N-th roots        */
+    double scale;
+    uint64_t seed;
+    uint64_t cdt[38];           /* cumulative table of chi (see zinc_keygen)  */
+    size_t plaintext_bytes;     /* L*N*8 per plaintext                        */
+    size_t ciphertext_bytes;    /* 2*L*N*8 per ciphertext                     */
+    int keyed;                  /* zinc_keygen done                           */
+    int precomputed;            /* zinc_precompute done                       */
+} zinc_info;
+
+/* Create a context on the current HIP device: validate the parameters, derive
+ * the moduli and roots, build the twiddle, FFT and sampler tables and upload
+ * them (synchronously).  ZINC_E_PARAM on invalid parameters. */
+zinc_status zinc_ctx_create(const zinc_params* p, zinc_ctx** out);
+/* Free everything the context owns (synchronises the device first). */
+zinc_status zinc_ctx_destroy(zinc_ctx* ctx);
+zinc_status zinc_ctx_info(const zinc_ctx* ctx, zinc_info* out);
+
+/* Gen (Eq. 7): s <- R_2 (uniform ternary), a <- R_q (uniform, drawn directly in
+ * the NTT domain), e <- chi; pk1 = [-a s + e]_q, pk2 = a, over all M moduli.
+ * chi is the discrete Gaussian of standard deviation 3.2 on [-19, 19],
+ * sampled by inverting a 38-entry cumulative table with one 64-bit uniform.
+ * Keys stay on the device.  Synchronous with respect to `stream`'s completion
+ * only when the caller synchronises. */
+zinc_status zinc_keygen(zinc_ctx* ctx, void* stream);
+
+/* Zinc precomputation (Scheme Description, "Precomputation"): cache a single
+ * Enc(0), a vanilla encryption of the zero plaintext under ZINC_ZERO_ID.
+ * ZINC_E_STATE before zinc_keygen. */
+zinc_status zinc_precompute(zinc_ctx* ctx, void* stream);
+
+/* CKKS encoding (canonical embedding; the paper defers to the CKKS paper):
+ * slot j <-> root zeta^(5^j mod 2N), zeta = exp(i pi/N);
+ * m_i = round_half_even((2 Delta / N) Re sum_j z_j zeta^(-i 5^j)), reduced per
+ * data limb.  d_slots [batch][n_slots] -> d_pt [batch][L][N].
+ * ZINC_E_RANGE if n_slots > N/2. */
+zinc_status zinc_encode(zinc_ctx* ctx, const double* d_slots, uint32_t n_slots, uint32_t batch,
+                        uint64_t* d_pt, void* stream);
+
+/* Vanilla encryption, Eq. 8 with pk2 in c2 (as the correctness proof of
+ * Theorem 1 uses it): u <- R_2, e1, e2 <- chi;
+ * c1 = [pk1 u + e1 + m]_q, c2 = [pk2 u + e2]_q.
+ * d_pt [batch][L][N] -> d_ct [batch][2][L][N].  ZINC_E_STATE before keygen. */
+zinc_status zinc_encrypt_vanilla(zinc_ctx* ctx, const uint64_t* d_pt, uint32_t batch,
+                                 const uint64_t* d_ct_ids, uint64_t* d_ct, void* stream);
+
+/* Zinc encryption, Algorithm 1: c = zero + m; e1', e2' <- chi;
+ * c' = ([c1 + e1']_q, [c2 + e2']_q), with `zero` the cached Enc(0).
+ * d_pt [batch][L][N] -> d_ct [batch][2][L][N].  ZINC_E_STATE before precompute. */
+zinc_status zinc_encrypt(zinc_ctx* ctx, const uint64_t* d_pt, uint32_t batch,
+                         const uint64_t* d_ct_ids, uint64_t* d_ct, void* stream);
+
+/* Encode and encrypt in one fused launch (scheme = ZINC_SCHEME_VANILLA or
+ * ZINC_SCHEME_ZINC): the result is bit-identical to zinc_encode followed by
+ * zinc_encrypt_vanilla / zinc_encrypt.  d_slots [batch][n_slots]. */
+zinc_status zinc_encrypt_slots(zinc_ctx* ctx, int scheme, const double* d_slots, uint32_t n_slots,
+                               uint32_t batch, const uint64_t* d_ct_ids, uint64_t* d_ct,
+                               void* stream);
+
+/* Decryption Dec(c) = [c1 + c2 sk]_q (the equation after Algorithm 1), back to
+ * the coefficient domain: d_ct [batch][2][L][N] -> d_pt [batch][L][N]. */
+zinc_status zinc_decrypt(zinc_ctx* ctx, const uint64_t* d_ct, uint32_t batch, uint64_t* d_pt,
+                         void* stream);
+
+/* CKKS decoding: centred lift of limb 0 (valid while every coefficient is
+ * below q_0/2 in magnitude; violations set the device error flag), then
+ * z_j = Re m(zeta^(5^j)) / Delta.  d_pt [batch][L][N] -> d_slots [batch][N/2]. */
+zinc_status zinc_decode(zinc_ctx* ctx, const uint64_t* d_pt, uint32_t batch, double* d_slots,
+                        void* stream);
+
+/* Homomorphic addition (Eq. 2): out = a + b component-wise mod q_l.
+ * All three are [batch][2][L][N]; out may alias a or b. */
+zinc_status zinc_add(zinc_ctx* ctx, const uint64_t* d_a, const uint64_t* d_b, uint32_t batch,
+                     uint64_t* d_out, void* stream);
+
+/* Read and clear the context's sticky device error flags (synchronises the
+ * device): bit 0 = slot magnitude out of range in encode, bit 1 = coefficient
+ * outside the limb-0 lift range in decode. */
+zinc_status zinc_device_errors(zinc_ctx* ctx, uint32_t* flags);
+
+/* ---- mixed-shape batches (one persistent launch over several contexts) ----
+ * An item names a context (index into ctxs), the float64 offset of its slot
+ * vector (N/2 values of its ring degree) in the slot buffer, the uint64 offset
+ * of its ciphertext ([2][L][N] of its context) in the ciphertext buffer, and its
+ * ct_id.  zinc_plan_create copies the items to the device and sorts them by
+ * cost; the plan keeps pointers to the contexts, which must outlive it.
+ * zinc_plan_launch encrypts every item in one launch (the first launch on a
+ * stream captures a HIP graph, later launches replay it when the buffers are
+ * the same).  The buffers must stay valid until the launch completes. */
+typedef struct zinc_item {
+    uint32_t ctx_idx;
+    uint32_t reserved;
+    uint64_t slot_off;
+    uint64_t ct_off;
+    uint64_t ct_id;
+} zinc_item;
+
+zinc_status zinc_plan_create(zinc_ctx* const* ctxs, uint32_t n_ctx, const zinc_item* items,
+                             uint32_t n_items, int scheme, zinc_plan** out);
+zinc_status zinc_plan_launch(zinc_plan* plan, const double* d_slots, uint64_t* d_ct, void* stream);
+zinc_status zinc_plan_destroy(zinc_plan* plan);
+
+/* ---- kernel-level entry points (parity testing of single steps) ---------- */
+
+/* In-place forward / inverse negacyclic NTT of d_poly [n_polys][N] modulo the
+ * context's modulus `limb` (0..M-1), in the order described above. */
+zinc_status zinc_ntt_forward(zinc_ctx* ctx, uint32_t limb, uint64_t* d_poly, uint32_t n_polys,
+                             void* stream);
+zinc_status zinc_ntt_inverse(zinc_ctx* ctx, uint32_t limb, uint64_t* d_poly, uint32_t n_polys,
+                             void* stream);
+
+/* Draw the samplers' output for `batch` identifiers: kind 0 = R_2 ternary,
+ * kind 1 = chi, as int64 [batch][N]; kind 2 = R_q uniform for modulus `limb`,
+ * as uint64 [batch][N].  `tag` is the stream tag (1..255). */
+zinc_status zinc_sample(zinc_ctx* ctx, int kind, uint32_t tag, uint32_t limb,
+                        const uint64_t* d_ct_ids, uint32_t batch, void* d_out, void* stream);
+
+/* Copy the device-resident keys and cache (device-to-device, on `stream`):
+ * secret key s_hat [M][N], public key [2][M][N], cached Enc(0) [2][L][N]. */
+zinc_status zinc_export_keys(zinc_ctx* ctx, uint64_t* d_sk, uint64_t* d_pk, uint64_t* d_zero,
+                             void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ZINC_H */

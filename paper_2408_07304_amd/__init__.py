@@ -1,0 +1,281 @@
+"""Python binding of libzinc (include/zinc.h): batched CKKS vanilla encryption
+(Eq. 8) and Zinc encryption (Algorithm 1) on MI355X.
+
+Argument marshalling only: every step runs in the HIP library.  Device
+buffers are torch tensors (uint64 data is carried in int64 tensors); streams
+are torch streams.  Importing this package does not load the library; the
+first call does, and raises if libzinc.so has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libzinc.so")
+
+ZINC_OK = 0
+ZINC_E_INVAL, ZINC_E_PARAM, ZINC_E_STATE, ZINC_E_NOMEM, ZINC_E_HIP, ZINC_E_RANGE = -1, -2, -3, -4, -5, -6
+ZINC_KEY_ID = (1 << 64) - 1
+ZINC_ZERO_ID = (1 << 64) - 2
+ZINC_MAX_MODULI = 32
+ZINC_SCHEME_VANILLA, ZINC_SCHEME_ZINC = 0, 1
+SAMPLE_TERNARY, SAMPLE_GAUSSIAN, SAMPLE_UNIFORM = 0, 1, 2
+
+_STATUS_NAMES = {-1: "ZINC_E_INVAL", -2: "ZINC_E_PARAM", -3: "ZINC_E_STATE", -4: "ZINC_E_NOMEM",
+                 -5: "ZINC_E_HIP", -6: "ZINC_E_RANGE"}
+
+
+class ZincError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class zinc_params(ctypes.Structure):
+    _fields_ = [("log_n", ctypes.c_uint32), ("n_moduli", ctypes.c_uint32),
+                ("bit_sizes", ctypes.POINTER(ctypes.c_uint32)), ("moduli", ctypes.POINTER(ctypes.c_uint64)),
+                ("scale", ctypes.c_double), ("sigma", ctypes.c_double), ("seed", ctypes.c_uint64)]
+
+
+class zinc_info(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint32), ("log_n", ctypes.c_uint32), ("n_moduli", ctypes.c_uint32),
+                ("limbs", ctypes.c_uint32), ("moduli", ctypes.c_uint64 * ZINC_MAX_MODULI),
+                ("psi", ctypes.c_uint64 * ZINC_MAX_MODULI), ("scale", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("cdt", ctypes.c_uint64 * 38),
+                ("plaintext_bytes", ctypes.c_size_t), ("ciphertext_bytes", ctypes.c_size_t),
+                ("keyed", ctypes.c_int), ("precomputed", ctypes.c_int)]
+
+
+class zinc_item(ctypes.Structure):
+    _fields_ = [("ctx_idx", ctypes.c_uint32), ("reserved", ctypes.c_uint32), ("slot_off", ctypes.c_uint64),
+                ("ct_off", ctypes.c_uint64), ("ct_id", ctypes.c_uint64)]
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_u32 = ctypes.c_uint32
+_SIGS = {
+    "zinc_last_error": (ctypes.c_char_p, []),
+    "zinc_ctx_create": (ctypes.c_int, [ctypes.POINTER(zinc_params), ctypes.POINTER(_vp)]),
+    "zinc_ctx_destroy": (ctypes.c_int, [_vp]),
+    "zinc_ctx_info": (ctypes.c_int, [_vp, ctypes.POINTER(zinc_info)]),
+    "zinc_keygen": (ctypes.c_int, [_vp, _vp]),
+    "zinc_precompute": (ctypes.c_int, [_vp, _vp]),
+    "zinc_encode": (ctypes.c_int, [_vp, _vp, _u32, _u32, _vp, _vp]),
+    "zinc_encrypt_vanilla": (ctypes.c_int, [_vp, _vp, _u32, _vp, _vp, _vp]),
+    "zinc_encrypt": (ctypes.c_int, [_vp, _vp, _u32, _vp, _vp, _vp]),
+    "zinc_encrypt_slots": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _u32, _u32, _vp, _vp, _vp]),
+    "zinc_decrypt": (ctypes.c_int, [_vp, _vp, _u32, _vp, _vp]),
+    "zinc_decode": (ctypes.c_int, [_vp, _vp, _u32, _vp, _vp]),
+    "zinc_add": (ctypes.c_int, [_vp, _vp, _vp, _u32, _vp, _vp]),
+    "zinc_device_errors": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_uint32)]),
+    "zinc_plan_create": (ctypes.c_int, [ctypes.POINTER(_vp), _u32, ctypes.POINTER(zinc_item), _u32,
+                                        ctypes.c_int, ctypes.POINTER(_vp)]),
+    "zinc_plan_launch": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "zinc_plan_destroy": (ctypes.c_int, [_vp]),
+    "zinc_ntt_forward": (ctypes.c_int, [_vp, _u32, _vp, _u32, _vp]),
+    "zinc_ntt_inverse": (ctypes.c_int, [_vp, _u32, _vp, _u32, _vp]),
+    "zinc_sample": (ctypes.c_int, [_vp, ctypes.c_int, _u32, _u32, _vp, _u32, _vp, _vp]),
+    "zinc_export_keys": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
+}
+EXPORTED = tuple(_SIGS)
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libzinc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        # One HIP runtime per process: torch brings its own libamdhip64
+        # (soname libamdhip64.so.7).  Importing torch first makes the dynamic
+        # loader resolve libzinc's dependency to that same, already-loaded
+        # runtime instead of mapping a second copy from /opt/rocm.
+        import torch  # noqa: F401
+        if not os.path.exists(path):
+            raise ImportError(f"{path} is missing: build it with `python -m paper_2408_07304_amd.build` "
+                              "(or __graft_entry__.build()); there is no fallback path")
+        L = ctypes.CDLL(path)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return load_library().zinc_last_error().decode()
+
+
+def _check(status: int):
+    if status != ZINC_OK:
+        raise ZincError(status, last_error())
+
+
+def _ptr(t):
+    """Device pointer of a tensor (or None)."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    if not t.is_contiguous():
+        raise ValueError("device buffers must be contiguous")
+    return t.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _u64_tensor(values, device):
+    import numpy as np
+    import torch
+    a = np.asarray(values, dtype=np.uint64).view(np.int64)
+    return torch.from_numpy(a.copy()).to(device)
+
+
+class Context:
+    """One parameter set (ring degree, moduli chain, scale, seed) with its
+    device-resident tables, keys and Zinc cache."""
+
+    def __init__(self, log_n: int, bits=None, scale: float = 2.0 ** 40, seed: int = 0, moduli=None,
+                 sigma: float = 3.2):
+        lib = load_library()
+        p = zinc_params()
+        p.log_n = log_n
+        count = len(moduli) if moduli is not None else len(bits)
+        p.n_moduli = count
+        self._bits = (ctypes.c_uint32 * count)(*(bits or [0] * count))
+        self._mods = (ctypes.c_uint64 * count)(*(moduli or [0] * count))
+        p.bit_sizes = self._bits if bits is not None else None
+        p.moduli = self._mods if moduli is not None else None
+        p.scale = scale
+        p.sigma = sigma
+        p.seed = seed
+        h = _vp()
+        _check(lib.zinc_ctx_create(ctypes.byref(p), ctypes.byref(h)))
+        self.handle = h.value
+        inf = self.info()
+        self.n, self.log_n, self.M, self.L = inf["n"], inf["log_n"], inf["n_moduli"], inf["limbs"]
+        self.moduli, self.psi, self.scale, self.seed = inf["moduli"], inf["psi"], inf["scale"], inf["seed"]
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load_library().zinc_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        i = zinc_info()
+        _check(load_library().zinc_ctx_info(self.handle, ctypes.byref(i)))
+        M = i.n_moduli
+        return {"n": i.n, "log_n": i.log_n, "n_moduli": M, "limbs": i.limbs,
+                "moduli": [int(x) for x in i.moduli[:M]], "psi": [int(x) for x in i.psi[:M]],
+                "scale": i.scale, "seed": int(i.seed), "cdt": [int(x) for x in i.cdt],
+                "plaintext_bytes": int(i.plaintext_bytes), "ciphertext_bytes": int(i.ciphertext_bytes),
+                "keyed": bool(i.keyed), "precomputed": bool(i.precomputed)}
+
+    # -- the scheme ---------------------------------------------------------
+    def keygen(self, stream=None):
+        _check(load_library().zinc_keygen(self.handle, _stream(stream)))
+
+    def precompute(self, stream=None):
+        _check(load_library().zinc_precompute(self.handle, _stream(stream)))
+
+    def encode(self, slots, out, stream=None):
+        b = slots.shape[0]
+        _check(load_library().zinc_encode(self.handle, _ptr(slots), slots.shape[1], b, _ptr(out), _stream(stream)))
+        return out
+
+    def encrypt_vanilla(self, pt, ct_ids, out, stream=None):
+        _check(load_library().zinc_encrypt_vanilla(self.handle, _ptr(pt), pt.shape[0], _ptr(ct_ids), _ptr(out),
+                                                   _stream(stream)))
+        return out
+
+    def encrypt(self, pt, ct_ids, out, stream=None):
+        _check(load_library().zinc_encrypt(self.handle, _ptr(pt), pt.shape[0], _ptr(ct_ids), _ptr(out),
+                                           _stream(stream)))
+        return out
+
+    def encrypt_slots(self, scheme: int, slots, ct_ids, out, stream=None):
+        _check(load_library().zinc_encrypt_slots(self.handle, scheme, _ptr(slots), slots.shape[1],
+                                                 slots.shape[0], _ptr(ct_ids), _ptr(out), _stream(stream)))
+        return out
+
+    def decrypt(self, ct, out, stream=None):
+        _check(load_library().zinc_decrypt(self.handle, _ptr(ct), ct.shape[0], _ptr(out), _stream(stream)))
+        return out
+
+    def decode(self, pt, out, stream=None):
+        _check(load_library().zinc_decode(self.handle, _ptr(pt), pt.shape[0], _ptr(out), _stream(stream)))
+        return out
+
+    def add(self, a, b, out, stream=None):
+        _check(load_library().zinc_add(self.handle, _ptr(a), _ptr(b), a.shape[0], _ptr(out), _stream(stream)))
+        return out
+
+    def device_errors(self) -> int:
+        f = ctypes.c_uint32()
+        _check(load_library().zinc_device_errors(self.handle, ctypes.byref(f)))
+        return int(f.value)
+
+    # -- kernel-level entry points -----------------------------------------
+    def ntt_forward(self, limb: int, poly, stream=None):
+        _check(load_library().zinc_ntt_forward(self.handle, limb, _ptr(poly), poly.shape[0], _stream(stream)))
+        return poly
+
+    def ntt_inverse(self, limb: int, poly, stream=None):
+        _check(load_library().zinc_ntt_inverse(self.handle, limb, _ptr(poly), poly.shape[0], _stream(stream)))
+        return poly
+
+    def sample(self, kind: int, tag: int, limb: int, ct_ids, out, stream=None):
+        _check(load_library().zinc_sample(self.handle, kind, tag, limb, _ptr(ct_ids), ct_ids.shape[0],
+                                          _ptr(out), _stream(stream)))
+        return out
+
+    def export_keys(self, sk=None, pk=None, zero=None, stream=None):
+        _check(load_library().zinc_export_keys(self.handle, _ptr(sk), _ptr(pk), _ptr(zero), _stream(stream)))
+
+
+class Plan:
+    """A mixed-shape batch over several contexts (zinc_plan_*)."""
+
+    def __init__(self, ctxs, items, scheme: int):
+        lib = load_library()
+        arr = (_vp * len(ctxs))(*[c.handle for c in ctxs])
+        its = (zinc_item * len(items))()
+        for i, (ci, so, co, cid) in enumerate(items):
+            its[i].ctx_idx, its[i].slot_off, its[i].ct_off, its[i].ct_id = int(ci), int(so), int(co), int(cid)
+        h = _vp()
+        _check(lib.zinc_plan_create(arr, len(ctxs), its, len(items), scheme, ctypes.byref(h)))
+        self.handle = h.value
+        self._ctxs = list(ctxs)
+
+    def launch(self, slots, ct, stream=None):
+        _check(load_library().zinc_plan_launch(self.handle, _ptr(slots), _ptr(ct), _stream(stream)))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load_library().zinc_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def context_for(ps) -> Context:
+    """Context of a workloads.ParamSet."""
+    return Context(ps.log_n, list(ps.bits), ps.scale, ps.seed)

@@ -1,0 +1,382 @@
+// Device building blocks for gfx950: 64-bit modular arithmetic (Shoup),
+// Philox4x32-10, the three samplers, the register/LDS negacyclic NTT and the
+// FP64 FFT of the CKKS canonical embedding.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "zinc_internal.h"
+
+namespace zinc {
+
+typedef uint64_t u64;
+
+// ---------------------------------------------------------------------------
+// modular arithmetic.  All moduli are below 2^60, so values up to 4q fit in
+// 64 bits with room for Harvey's lazy reduction.
+// ---------------------------------------------------------------------------
+
+// y * w mod q in [0, 2q), for any y < 2^64, w < q, wp = floor(w 2^64 / q).
+__device__ __forceinline__ u64 shoup_lazy(u64 y, u64 w, u64 wp, u64 q) {
+    return y * w - __umul64hi(y, wp) * q;
+}
+
+__device__ __forceinline__ u64 csub(u64 x, u64 m) { return x >= m ? x - m : x; }
+
+// [0, 4q) -> [0, q)
+__device__ __forceinline__ u64 canon4(u64 x, u64 q, u64 q2) { return csub(csub(x, q2), q); }
+
+__device__ __forceinline__ u64 addmod(u64 a, u64 b, u64 q) { return csub(a + b, q); }
+
+// residue of a signed 64-bit integer with |x| < 2^63
+__device__ __forceinline__ u64 reduce_signed(long long x, const LimbConst& lc) {
+    const u64 a = x < 0 ? (u64)(-x) : (u64)x;
+    u64 r = csub(a - __umul64hi(a, lc.bar) * lc.q, lc.q);
+    return (x < 0 && r != 0) ? lc.q - r : r;
+}
+
+// residue of a small signed integer (|x| < q)
+__device__ __forceinline__ u64 small_mod(int x, u64 q) {
+    return x < 0 ? q - (u64)(unsigned)(-x) : (u64)(unsigned)x;
+}
+
+// Cooley-Tukey butterfly with Harvey's lazy reduction: x, y in [0, 4q) ->
+// (x + y w, x - y w) in [0, 4q).
+__device__ __forceinline__ void ct_bfly(u64& x, u64& y, u64 w, u64 wp, u64 q, u64 q2) {
+    const u64 a = csub(x, q2);
+    const u64 t = shoup_lazy(y, w, wp, q);
+    x = a + t;
+    y = a - t + q2;
+}
+
+// Gentleman-Sande butterfly: x, y in [0, 2q) -> (x + y, (x - y) w) in [0, 2q).
+__device__ __forceinline__ void gs_bfly(u64& x, u64& y, u64 w, u64 wp, u64 q, u64 q2) {
+    const u64 a = csub(x + y, q2);
+    const u64 d = x - y + q2;
+    y = shoup_lazy(d, w, wp, q);
+    x = a;
+}
+
+// remainder of (hi 2^64 + lo) by q (hi < q): restoring long division.  Slow;
+// used only at key generation.
+__device__ __forceinline__ u64 mod128(u64 hi, u64 lo, u64 q) {
+    u64 r = hi;
+    for (int i = 63; i >= 0; --i) {
+        const u64 top = r >> 63;
+        r = (r << 1) | ((lo >> i) & 1);
+        if (top || r >= q) r -= q;
+    }
+    return r;
+}
+
+// floor(w 2^64 / q) for w < q (Shoup companion), by long division.
+__device__ __forceinline__ u64 shoup_companion_dev(u64 w, u64 q) {
+    u64 r = w, quo = 0;
+    for (int i = 63; i >= 0; --i) {
+        const u64 top = r >> 63;
+        r <<= 1;
+        quo <<= 1;
+        if (top || r >= q) { r -= q; quo |= 1; }
+    }
+    return quo;
+}
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): counter (c0, c1, c2, c3),
+// key (k0, k1); ten rounds, Weyl key schedule.
+// ---------------------------------------------------------------------------
+struct U4 {
+    uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                     uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+        const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+        c0 = hi1 ^ c1 ^ k0;
+        c1 = lo1;
+        c2 = hi0 ^ c3 ^ k1;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return U4{c0, c1, c2, c3};
+}
+
+__device__ __forceinline__ U4 draw(u64 seed, u64 ct_id, uint32_t tag, uint32_t limb, uint32_t block) {
+    return philox(block, (tag & 0xFFu) | ((limb & 0xFFu) << 8), (uint32_t)ct_id,
+                  (uint32_t)(ct_id >> 32), (uint32_t)seed, (uint32_t)(seed >> 32));
+}
+
+// chi: x = -19 + #{i < 38 : U >= T[i]}; branch-free scan of the table.
+__device__ __forceinline__ int gauss_from(u64 u, const u64* __restrict__ cdt) {
+    int cnt = 0;
+#pragma unroll
+    for (int i = 0; i < kCdtLen; ++i) cnt += (u >= cdt[i]) ? 1 : 0;
+    return cnt - kTail;
+}
+
+// R_2: x = floor(3 w / 2^32) - 1
+__device__ __forceinline__ int ternary_from(uint32_t w) { return (int)__umulhi(w, 3u) - 1; }
+
+// ---------------------------------------------------------------------------
+// NTT geometry: N = 2^LOGN coefficients over T = 2^LOGT threads, R = N/T per
+// thread in registers.  The log N stages are split into NPASS passes of at
+// most LOGR stages; pass p acts on index bits [LO(p), H(p)).  In pass p,
+// thread t holds the R indices formed by putting the pass's active bits (the
+// low K(p) bits of the register number c) at [LO, H) and the remaining bits --
+// first the thread id, then the high bits of c -- at the other positions,
+// lowest first.  Passes are joined by exchanges through LDS.
+// ---------------------------------------------------------------------------
+template <int LOGN_, int LOGT_>
+struct Geom {
+    static constexpr int LOGN = LOGN_, LOGT = LOGT_;
+    static constexpr int N = 1 << LOGN, T = 1 << LOGT;
+    static constexpr int LOGR = LOGN - LOGT, R = 1 << LOGR;
+    static constexpr int NPASS = (LOGN + LOGR - 1) / LOGR;
+    static constexpr int H_ = N / 2;
+    __host__ __device__ static constexpr int K(int p) { return LOGN / NPASS + (p < LOGN % NPASS ? 1 : 0); }
+    __host__ __device__ static constexpr int H(int p) { return p == 0 ? LOGN : H(p - 1) - K(p - 1); }
+    __host__ __device__ static constexpr int LO(int p) { return H(p) - K(p); }
+    __host__ __device__ static constexpr uint32_t spread(int p, uint32_t na) {
+        return (na & ((1u << LO(p)) - 1u)) | ((na >> LO(p)) << H(p));
+    }
+    __host__ __device__ static constexpr uint32_t cpart(int p, int c) {
+        return ((uint32_t)(c & ((1 << K(p)) - 1)) << LO(p)) |
+               spread(p, (uint32_t)(c >> K(p)) << LOGT);
+    }
+    __device__ static __forceinline__ uint32_t tpart(int p, uint32_t t) { return spread(p, t); }
+    static_assert(LOGR >= 2, "at least 4 coefficients per thread");
+    static_assert(LOGN / NPASS + (LOGN % NPASS ? 1 : 0) <= LOGR, "pass wider than a thread's registers");
+};
+
+// LDS address swizzle: XOR of the low four index bits with the next four,
+// which keeps every pass's access pattern free of bank conflicts.
+__device__ __forceinline__ uint32_t swz(uint32_t i) { return i ^ ((i >> 4) & 15u); }
+
+template <class G, int P>
+__device__ __forceinline__ void fwd_pass(u64 (&v)[G::R], uint32_t tp, const u64* __restrict__ tw,
+                                         u64 q, u64 q2) {
+    constexpr int K = G::K(P), LO = G::LO(P), HH = G::H(P);
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const int b = K - 1 - i;                 // local bit of this stage
+        const int s = G::LOGN - HH + i;          // global stage index
+#pragma unroll
+        for (int c = 0; c < G::R; ++c) {
+            if (c & (1 << b)) continue;
+            const uint32_t j = (P == 0 ? 0u : tp) | G::cpart(P, c);
+            const uint32_t ti = (1u << s) + (j >> (LO + b + 1));
+            ct_bfly(v[c], v[c | (1 << b)], tw[2 * ti], tw[2 * ti + 1], q, q2);
+        }
+    }
+}
+
+template <class G, int P>
+__device__ __forceinline__ void inv_pass(u64 (&v)[G::R], uint32_t tp, const u64* __restrict__ itw,
+                                         u64 q, u64 q2) {
+    constexpr int K = G::K(P), LO = G::LO(P);
+#pragma unroll
+    for (int b = 0; b < K; ++b) {
+        const int s = G::LOGN - 1 - (LO + b);
+#pragma unroll
+        for (int c = 0; c < G::R; ++c) {
+            if (c & (1 << b)) continue;
+            const uint32_t j = (P == 0 ? 0u : tp) | G::cpart(P, c);
+            const uint32_t ti = (1u << s) + (j >> (LO + b + 1));
+            gs_bfly(v[c], v[c | (1 << b)], itw[2 * ti], itw[2 * ti + 1], q, q2);
+        }
+    }
+}
+
+template <class G, int P>
+__device__ __forceinline__ void lds_put(u64* lds, const u64 (&v)[G::R], uint32_t t) {
+    const uint32_t tp = G::tpart(P, t);
+#pragma unroll
+    for (int c = 0; c < G::R; ++c) lds[swz(tp | G::cpart(P, c))] = v[c];
+}
+
+template <class G, int P>
+__device__ __forceinline__ void lds_get(const u64* lds, u64 (&v)[G::R], uint32_t t) {
+    const uint32_t tp = G::tpart(P, t);
+#pragma unroll
+    for (int c = 0; c < G::R; ++c) v[c] = lds[swz(tp | G::cpart(P, c))];
+}
+
+template <class G, int P>
+__device__ __forceinline__ void fwd_rest(u64 (&v)[G::R], u64* lds, const u64* __restrict__ tw, u64 q,
+                                         u64 q2, uint32_t t) {
+    if constexpr (P < G::NPASS) {
+        __syncthreads();
+        lds_put<G, P - 1>(lds, v, t);
+        __syncthreads();
+        lds_get<G, P>(lds, v, t);
+        fwd_pass<G, P>(v, G::tpart(P, t), tw, q, q2);
+        fwd_rest<G, P + 1>(v, lds, tw, q, q2, t);
+    }
+}
+
+// Forward NTT: v in pass-0 layout with values in [0, 4q) -> v in the last
+// pass's layout with values in [0, 4q).  Uses lds[N] as exchange buffer.
+template <class G>
+__device__ __forceinline__ void ntt_fwd(u64 (&v)[G::R], u64* lds, const u64* __restrict__ tw, u64 q,
+                                        u64 q2, uint32_t t) {
+    fwd_pass<G, 0>(v, 0u, tw, q, q2);
+    fwd_rest<G, 1>(v, lds, tw, q, q2, t);
+}
+
+template <class G, int P>
+__device__ __forceinline__ void inv_rest(u64 (&v)[G::R], u64* lds, const u64* __restrict__ itw, u64 q,
+                                         u64 q2, uint32_t t) {
+    if constexpr (P >= 0) {
+        __syncthreads();
+        lds_put<G, P + 1>(lds, v, t);
+        __syncthreads();
+        lds_get<G, P>(lds, v, t);
+        inv_pass<G, P>(v, G::tpart(P, t), itw, q, q2);
+        inv_rest<G, P - 1>(v, lds, itw, q, q2, t);
+    }
+}
+
+// Inverse NTT without the N^-1 factor: v in the last pass's layout with values
+// in [0, 2q) -> v in pass-0 layout with values in [0, 2q).
+template <class G>
+__device__ __forceinline__ void ntt_inv(u64 (&v)[G::R], u64* lds, const u64* __restrict__ itw, u64 q,
+                                        u64 q2, uint32_t t) {
+    constexpr int PL = G::NPASS - 1;
+    inv_pass<G, PL>(v, G::tpart(PL, t), itw, q, q2);
+    inv_rest<G, PL - 1>(v, lds, itw, q, q2, t);
+}
+
+// Write v (last forward pass layout) to LDS so that lds[swz(i)] is coefficient i.
+template <class G>
+__device__ __forceinline__ void to_natural(u64* lds, const u64 (&v)[G::R], uint32_t t) {
+    __syncthreads();
+    lds_put<G, G::NPASS - 1>(lds, v, t);
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// samplers in pass-0 layout.  Coefficient k of an N-draw of chi uses half
+// k / (N/2) of Philox block k mod N/2; of R_2, word k / (N/4) of block
+// k mod N/4.  In pass-0 layout the top two index bits are the top two active
+// bits of the register number, so a thread owns every coefficient of the
+// blocks it draws.
+// ---------------------------------------------------------------------------
+template <int R>
+struct Packed8 {
+    uint32_t w[R / 4];
+    __device__ __forceinline__ void clear() {
+#pragma unroll
+        for (int i = 0; i < R / 4; ++i) w[i] = 0;
+    }
+    __device__ __forceinline__ void set(int c, int x) { w[c >> 2] |= ((uint32_t)(x & 0xFF)) << (8 * (c & 3)); }
+    __device__ __forceinline__ int get(int c) const { return (int)(int8_t)(uint8_t)(w[c >> 2] >> (8 * (c & 3))); }
+};
+
+template <class G>
+__device__ __forceinline__ void sample_gauss_p0(Packed8<G::R>& out, const DevParams& p, u64 ct_id,
+                                                uint32_t tag, uint32_t t) {
+    constexpr int TOP = 1 << (G::K(0) - 1);
+    const uint32_t tp = G::tpart(0, t);
+    out.clear();
+#pragma unroll
+    for (int c = 0; c < G::R; ++c) {
+        if (c & TOP) continue;
+        const uint32_t k = tp | G::cpart(0, c);   // < N/2
+        const U4 r = draw(p.seed, ct_id, tag, 0, k);
+        out.set(c, gauss_from((u64)r.x | ((u64)r.y << 32), p.cdt));
+        out.set(c | TOP, gauss_from((u64)r.z | ((u64)r.w << 32), p.cdt));
+    }
+}
+
+template <class G>
+__device__ __forceinline__ void sample_ternary_p0(Packed8<G::R>& out, const DevParams& p, u64 ct_id,
+                                                  uint32_t tag, uint32_t t) {
+    constexpr int SH = G::K(0) - 2;
+    constexpr int TOP2 = 3 << SH;
+    const uint32_t tp = G::tpart(0, t);
+    out.clear();
+#pragma unroll
+    for (int c = 0; c < G::R; ++c) {
+        if (c & TOP2) continue;
+        const uint32_t k = tp | G::cpart(0, c);   // < N/4
+        const U4 r = draw(p.seed, ct_id, tag, 0, k);
+        out.set(c, ternary_from(r.x));
+        out.set(c | (1 << SH), ternary_from(r.y));
+        out.set(c | (2 << SH), ternary_from(r.z));
+        out.set(c | (3 << SH), ternary_from(r.w));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 FFT for the canonical embedding: radix-2 decimation in time over
+// H = N/2 points held in LDS, input in bit-reversed order, output natural.
+// sign = -1: F[i] = sum_k A[k] exp(-2 pi i k i / H); sign = +1: conjugate roots.
+// ---------------------------------------------------------------------------
+struct C2 {
+    double x, y;
+};
+
+__device__ __forceinline__ C2 cmul(C2 a, C2 b) { return C2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+
+template <int LOGH, int T, int SIGN>
+__device__ __forceinline__ void fft_dit(C2* A, const double* __restrict__ fft_tw, uint32_t t) {
+    constexpr int H = 1 << LOGH;
+#pragma unroll 1
+    for (int s = 1; s <= LOGH; ++s) {
+        const int half = 1 << (s - 1);
+        for (int b = t; b < H / 2; b += T) {
+            const int pos = b & (half - 1);
+            const int i0 = ((b >> (s - 1)) << s) + pos, i1 = i0 + half;
+            const int ti = pos << (LOGH - s);
+            C2 w{fft_tw[2 * ti], fft_tw[2 * ti + 1]};
+            if (SIGN > 0) w.y = -w.y;
+            const C2 a = A[i0], bw = cmul(A[i1], w);
+            A[i0] = C2{a.x + bw.x, a.y + bw.y};
+            A[i1] = C2{a.x - bw.x, a.y - bw.y};
+        }
+        __syncthreads();
+    }
+}
+
+// CKKS encoding of one slot vector into the integer coefficients m held in
+// pass-0 layout: place Delta z_j at position (5^j mod 2N - 1)/4 of an N/2-point
+// vector, transform, twist by zeta^-i and scale by 2/N; coefficient i < N/2 is
+// the real part of entry i, coefficient i + N/2 its imaginary part; round half
+// to even.  Uses lds (N words) as the complex work array.
+template <class G>
+__device__ __forceinline__ void encode_p0(long long (&m)[G::R], u64* lds, const DevParams& p,
+                                          const double* __restrict__ z, uint32_t n_slots, uint32_t t) {
+    constexpr int H = G::N / 2, LOGH = G::LOGN - 1;
+    C2* A = reinterpret_cast<C2*>(lds);
+    __syncthreads();
+    for (uint32_t j = t; j < (uint32_t)H; j += G::T) {
+        const double val = j < n_slots ? p.scale * z[j] : 0.0;
+        A[p.slot_pos[j]] = C2{val, 0.0};
+    }
+    __syncthreads();
+    fft_dit<LOGH, G::T, -1>(A, p.fft_tw, t);
+    const double f = 2.0 / (double)G::N;
+    const uint32_t tp = G::tpart(0, t);
+    bool bad = false;
+#pragma unroll
+    for (int c = 0; c < G::R; ++c) {
+        const uint32_t idx = tp | G::cpart(0, c);
+        const uint32_t i = idx & (H - 1);
+        const C2 w = cmul(A[i], C2{p.twist[2 * i], p.twist[2 * i + 1]});
+        double x = (idx < (uint32_t)H ? w.x : w.y) * f;
+        x = __builtin_rint(x);
+        if (!(__builtin_fabs(x) < 4611686018427387904.0)) {   // 2^62 (also catches NaN)
+            bad = true;
+            x = 0.0;
+        }
+        m[c] = (long long)x;
+    }
+    if (bad) atomicOr(p.err, 1u);
+}
+
+}  // namespace zinc

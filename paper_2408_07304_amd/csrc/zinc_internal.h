@@ -1,0 +1,100 @@
+// Internal declarations shared by the host runtime (capi.cpp, host_math.cpp)
+// and the HIP kernel translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string>
+
+#include "../../include/zinc.h"
+
+namespace zinc {
+
+constexpr int kCdtLen = 38;       // support [-19, 19] -> 38 thresholds
+constexpr int kCdtPad = 64;       // padded to a power of two for the device search
+constexpr int kTail = 19;
+
+enum Tag : uint32_t { TAG_SK = 1, TAG_A = 2, TAG_EPK = 3, TAG_U = 4, TAG_E1 = 5, TAG_E2 = 6,
+                      TAG_E1Z = 7, TAG_E2Z = 8 };
+
+// Per-modulus constants read by the kernels (one entry per limb).
+struct LimbConst {
+    uint64_t q;         // modulus
+    uint64_t q2;        // 2q
+    uint64_t bar;       // floor(2^64 / q): Shoup companion of 1, used to reduce < 2^64 values
+    uint64_t ninv;      // N^-1 mod q
+    uint64_t ninv_sh;   // Shoup companion of N^-1
+    uint64_t half;      // (q - 1) / 2, centred-lift threshold
+};
+
+// Everything a kernel needs about one parameter set, as device pointers.
+struct DevParams {
+    uint32_t log_n, n, M, L;
+    uint64_t seed;
+    double scale;
+    const LimbConst* limbs;       // [M]
+    const uint64_t* tw;           // [M][N][2]  (psi^brv(k), Shoup companion)
+    const uint64_t* itw;          // [M][N][2]  (psi^-brv(k), Shoup companion)
+    const double* fft_tw;         // [N/4][2]   exp(-2 pi i k / (N/2)), k < N/4
+    const double* twist;          // [N/2][2]   exp(-i pi k / N),       k < N/2
+    const uint32_t* slot_pos;     // [N/2]      brv_{log N - 1}((5^j mod 2N - 1) / 4)
+    const uint64_t* cdt;          // [kCdtPad]  cumulative table, padded with 2^64-1
+    const uint64_t* sk;           // [M][N]     s_hat
+    const uint64_t* sk_sh;        // [M][N]     Shoup companions of s_hat
+    const uint64_t* pk;           // [2][M][N]
+    const uint64_t* pk_sh;        // [2][M][N]
+    const uint64_t* zero;         // [2][L][N]  cached Enc(0)
+    uint32_t* err;                // sticky device error flags
+};
+
+}  // namespace zinc
+
+struct zinc_ctx {
+    int device = 0;
+    uint32_t log_n = 0, n = 0, M = 0, L = 0;
+    double scale = 0, sigma = 0;
+    uint64_t seed = 0;
+    uint64_t q[ZINC_MAX_MODULI] = {};
+    uint64_t psi[ZINC_MAX_MODULI] = {};
+    uint64_t cdt[zinc::kCdtLen] = {};
+    bool keyed = false, precomputed = false;
+    // device allocations owned by the context
+    void* d_block = nullptr;      // one allocation holding every table and key
+    zinc::DevParams dev{};
+};
+
+namespace zinc {
+
+// host_math.cpp
+bool is_prime(uint64_t n);
+bool choose_moduli(uint32_t log_n, uint32_t count, const uint32_t* bits, uint64_t* out);
+uint64_t smallest_psi(uint64_t q, uint32_t log_n);
+uint64_t mulmod_host(uint64_t a, uint64_t b, uint64_t q);
+uint64_t powmod_host(uint64_t b, uint64_t e, uint64_t q);
+uint64_t shoup_companion(uint64_t w, uint64_t q);
+void gaussian_cdt(double sigma, uint64_t out[kCdtLen]);
+
+void set_error(const std::string& msg);
+
+// kernel launchers (return hipError_t of the launch)
+hipError_t launch_keygen(const DevParams& p, uint64_t* sk, uint64_t* sk_sh, uint64_t* pk,
+                         uint64_t* pk_sh, hipStream_t s);
+hipError_t launch_encrypt_pt(const DevParams& p, int scheme, const uint64_t* pt, uint32_t batch,
+                             const uint64_t* ct_ids, uint64_t* ct, hipStream_t s);
+hipError_t launch_encrypt_slots(const DevParams& p, int scheme, const double* slots,
+                                uint32_t n_slots, uint32_t batch, const uint64_t* ct_ids,
+                                uint64_t* ct, hipStream_t s);
+hipError_t launch_encode(const DevParams& p, const double* slots, uint32_t n_slots, uint32_t batch,
+                         uint64_t* pt, hipStream_t s);
+hipError_t launch_decrypt(const DevParams& p, const uint64_t* ct, uint32_t batch, uint64_t* pt,
+                          hipStream_t s);
+hipError_t launch_decode(const DevParams& p, const uint64_t* pt, uint32_t batch, double* slots,
+                         hipStream_t s);
+hipError_t launch_add(const DevParams& p, const uint64_t* a, const uint64_t* b, uint32_t batch,
+                      uint64_t* out, hipStream_t s);
+hipError_t launch_ntt(const DevParams& p, bool inverse, uint32_t limb, uint64_t* poly,
+                      uint32_t n_polys, hipStream_t s);
+hipError_t launch_sample(const DevParams& p, int kind, uint32_t tag, uint32_t limb,
+                         const uint64_t* ct_ids, uint32_t batch, void* out, hipStream_t s);
+
+}  // namespace zinc

@@ -1,0 +1,365 @@
+"""GPU parity of the HIP path against the CPU oracle, through the C ABI.
+
+Bit-exact: tables, samplers, NTT/INTT, keys, the cached Enc(0), vanilla (Eq. 8)
+and Zinc (Algorithm 1) ciphertexts from a shared integer plaintext,
+decryption, homomorphic addition; the fused encode+encrypt launch equals
+encode followed by encrypt.  Within tolerance: FP64 encoding (integer
+coefficients equal except inside the rounding-tie window, where they may
+differ by one) and decoding (2^-20 in message units)."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2408_07304_amd as zinc
+from gpu_util import empty_u64, from_dev, gpu_ctx, ids, oracle_keys, to_dev, torch_cuda
+from paper_2408_07304_amd.workloads import PARAM_SETS, W_LARGE, W_MAIN, W_SMALL, make_slots
+
+pytestmark = pytest.mark.gpu
+
+NAMES = ["n4096", "n8192", "n16384"]
+SCHEMES = [zinc.ZINC_SCHEME_VANILLA, zinc.ZINC_SCHEME_ZINC]
+
+
+def say(msg):
+    print(f"[gpu] {msg}", flush=True)
+
+
+def tie_tau(n, xmax):
+    """Half-width of the window around x.5 inside which an FP64 evaluation of
+    the encoding sum may round either way: a generous multiple of the FFT's
+    error bound log2(N/2) * 2^-53 * max|x|."""
+    return 8 * np.log2(n) * 2.0 ** -53 * xmax + 2.0 ** -40
+
+
+def centred(pt0, q):
+    v = pt0.astype(object)
+    return np.array([int(x) - q if int(x) > q // 2 else int(x) for x in v], dtype=np.int64)
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_tables_match_oracle(name):
+    c = gpu_ctx(name)
+    P, sh, pk, zero = oracle_keys(name)
+    info = c.info()
+    assert info["moduli"] == P.moduli
+    assert info["psi"] == P.psi
+    assert info["cdt"] == [int(x) for x in P.cdt]
+    assert info["limbs"] == P.L and info["n"] == P.n
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_samplers_bit_exact(name):
+    c = gpu_ctx(name)
+    P = oracle_keys(name)[0]
+    idv = [0, 1, 12345, 2 ** 40 + 7, zinc.ZINC_ZERO_ID, zinc.ZINC_KEY_ID]
+    d_ids = ids(idv)
+    out = empty_u64(len(idv), P.n)
+    say(f"{name} sample ternary/gauss")
+    for kind, tag, fn in ((zinc.SAMPLE_TERNARY, oracle.TAG_U, oracle.sample_ternary),
+                          (zinc.SAMPLE_GAUSSIAN, oracle.TAG_E1Z, oracle.sample_gaussian)):
+        c.sample(kind, tag, 0, d_ids, out)
+        got = from_dev(out, np.int64)
+        for i, cid in enumerate(idv):
+            assert np.array_equal(got[i], fn(P.seed, cid, tag, P.n)), (kind, cid)
+    say(f"{name} sample uniform")
+    for limb in range(P.M):
+        c.sample(zinc.SAMPLE_UNIFORM, oracle.TAG_A, limb, d_ids[:2], out[:2])
+        got = from_dev(out[:2])
+        for i, cid in enumerate(idv[:2]):
+            assert np.array_equal(got[i], oracle.sample_uniform(P.seed, cid, oracle.TAG_A, limb, P.n,
+                                                                P.moduli[limb]))
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_ntt_bit_exact(name):
+    c = gpu_ctx(name)
+    P = oracle_keys(name)[0]
+    rng = np.random.default_rng(7)
+    for limb, q in enumerate(P.moduli):
+        a = rng.integers(0, q, size=(3, P.n), dtype=np.uint64)
+        a[0, :] = 0
+        a[0, 0] = 1                      # delta: transform is all ones
+        a[1, :] = q - 1                  # maximal residues
+        d = to_dev(a)
+        say(f"{name} ntt limb {limb}")
+        c.ntt_forward(limb, d)
+        got = from_dev(d)
+        for i in range(3):
+            assert np.array_equal(got[i], oracle.ntt_forward(a[i], P.log_n, q, P.psi[limb])), (limb, i)
+        assert np.all(got[0] == 1)
+        c.ntt_inverse(limb, d)
+        assert np.array_equal(from_dev(d), a)
+        b = rng.integers(0, q, size=(2, P.n), dtype=np.uint64)
+        d = to_dev(b)
+        c.ntt_inverse(limb, d)
+        got = from_dev(d)
+        for i in range(2):
+            assert np.array_equal(got[i], oracle.ntt_inverse(b[i], P.log_n, q, P.psi[limb]))
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_keys_and_cache_bit_exact(name):
+    c = gpu_ctx(name)
+    P, sh, pk, zero = oracle_keys(name)
+    dsk, dpk, dz = empty_u64(P.M, P.n), empty_u64(2, P.M, P.n), empty_u64(2, P.L, P.n)
+    c.export_keys(dsk, dpk, dz)
+    assert np.array_equal(from_dev(dsk), sh)
+    assert np.array_equal(from_dev(dpk), pk)
+    assert np.array_equal(from_dev(dz), zero)
+
+
+def _plaintexts(P, count, seed):
+    """Integer plaintexts: small signed coefficients and uniformly random residues."""
+    rng = np.random.default_rng(seed)
+    pts = []
+    for i in range(count):
+        if i % 2 == 0:
+            m = rng.integers(-(2 ** 40), 2 ** 40, size=P.n)
+            pts.append(oracle.to_rns(P, m))
+        else:
+            pts.append(np.stack([rng.integers(0, q, size=P.n, dtype=np.uint64) for q in P.data_moduli]))
+    return np.stack(pts)
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("name", NAMES)
+def test_encrypt_from_plaintext_bit_exact(name, scheme):
+    c = gpu_ctx(name)
+    P, sh, pk, zero = oracle_keys(name)
+    B = 5
+    pt = _plaintexts(P, B, 11 + scheme)
+    idv = [3, 0, 99, 2 ** 33 + 1, 7]
+    out = empty_u64(B, 2, P.L, P.n)
+    say(f"{name} encrypt scheme={scheme} from plaintext")
+    if scheme == zinc.ZINC_SCHEME_ZINC:
+        c.encrypt(to_dev(pt), ids(idv), out)
+    else:
+        c.encrypt_vanilla(to_dev(pt), ids(idv), out)
+    got = from_dev(out)
+    for i in range(B):
+        want = (oracle.encrypt_zinc(P, zero, pt[i], idv[i]) if scheme == zinc.ZINC_SCHEME_ZINC
+                else oracle.encrypt_vanilla(P, pk, pt[i], idv[i]))
+        assert np.array_equal(got[i], want), (i, idv[i])
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_encode_within_tie_window(name):
+    c = gpu_ctx(name)
+    P = oracle_keys(name)[0]
+    w = {"n4096": W_SMALL, "n8192": W_MAIN, "n16384": W_LARGE}[name]
+    z = make_slots(w, 3)
+    z[2, 100:] = 0.0                                     # also a partly empty vector
+    out = empty_u64(3, P.L, P.n)
+    say(f"{name} encode")
+    c.encode(to_dev(z), out)
+    got = from_dev(out)
+    mism = 0
+    for i in range(3):
+        m, fr = oracle.encode(P, z[i])
+        g = centred(got[i, 0], P.moduli[0])
+        d = g - m
+        assert np.abs(d).max() <= 1
+        tau = tie_tau(P.n, np.abs(m).max())
+        assert np.all(np.abs(np.abs(fr[d != 0]) - 0.5) <= tau)
+        mism += int((d != 0).sum())
+        for l in range(1, P.L):     # every limb holds the same integer
+            assert np.array_equal(got[i, l], oracle.to_rns(P, g, P.L)[l])
+    say(f"{name} encode: {mism} coefficients rounded the other way inside the tie window")
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("name", NAMES)
+def test_fused_equals_encode_then_encrypt(name, scheme):
+    c = gpu_ctx(name)
+    P = oracle_keys(name)[0]
+    z = make_slots(W_SMALL if name == "n4096" else W_MAIN, 6, PARAM_SETS[name])
+    B = z.shape[0]
+    d_ids = ids(range(40, 40 + B))
+    f = empty_u64(B, 2, P.L, P.n)
+    u = empty_u64(B, 2, P.L, P.n)
+    pt = empty_u64(B, P.L, P.n)
+    say(f"{name} fused vs unfused scheme={scheme}")
+    c.encrypt_slots(scheme, to_dev(z), d_ids, f)
+    c.encode(to_dev(z), pt)
+    if scheme == zinc.ZINC_SCHEME_ZINC:
+        c.encrypt(pt, d_ids, u)
+    else:
+        c.encrypt_vanilla(pt, d_ids, u)
+    assert np.array_equal(from_dev(f), from_dev(u))
+    # fewer slots than N/2 take the same path with zero padding
+    zs = np.ascontiguousarray(z[:, :33])
+    c.encrypt_slots(scheme, to_dev(zs), d_ids, f)
+    c.encode(to_dev(zs), pt)
+    (c.encrypt if scheme == zinc.ZINC_SCHEME_ZINC else c.encrypt_vanilla)(pt, d_ids, u)
+    assert np.array_equal(from_dev(f), from_dev(u))
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_decrypt_bit_exact(name):
+    c = gpu_ctx(name)
+    P, sh, pk, zero = oracle_keys(name)
+    pt = _plaintexts(P, 3, 5)
+    cts = np.stack([oracle.encrypt_zinc(P, zero, pt[0], 1), oracle.encrypt_vanilla(P, pk, pt[1], 2),
+                    oracle.encrypt_zinc(P, zero, pt[2], 3)])
+    out = empty_u64(3, P.L, P.n)
+    say(f"{name} decrypt")
+    c.decrypt(to_dev(cts), out)
+    got = from_dev(out)
+    for i in range(3):
+        assert np.array_equal(got[i], oracle.decrypt(P, sh, cts[i]))
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_decode_parity(name):
+    c = gpu_ctx(name)
+    P = oracle_keys(name)[0]
+    rng = np.random.default_rng(9)
+    z = rng.uniform(-1, 1, size=(2, P.n // 2))
+    ms = [oracle.encode(P, z[i])[0] for i in range(2)]
+    pt = np.stack([oracle.to_rns(P, m) for m in ms])
+    out = torch_cuda().empty((2, P.n // 2), dtype=torch_cuda().float64, device="cuda")
+    say(f"{name} decode")
+    c.decode(to_dev(pt), out)
+    got = from_dev(out, np.float64)
+    for i in range(2):
+        assert np.abs(got[i] - oracle.decode(P, ms[i])).max() <= 2.0 ** -20
+    assert c.device_errors() == 0
+
+
+def noise_bound(n, scale):
+    return (20 * n * 3.2 + 6 * (n / 24) ** 0.5) / scale
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("name", NAMES)
+def test_round_trip_within_noise_bound(name, scheme):
+    c = gpu_ctx(name)
+    P = oracle_keys(name)[0]
+    B = 4
+    z = np.random.default_rng(13).uniform(-1, 1, size=(B, P.n // 2))
+    ct = empty_u64(B, 2, P.L, P.n)
+    pt = empty_u64(B, P.L, P.n)
+    torch = torch_cuda()
+    zz = torch.empty((B, P.n // 2), dtype=torch.float64, device="cuda")
+    say(f"{name} round trip scheme={scheme}")
+    c.encrypt_slots(scheme, to_dev(z), ids(range(B)), ct)
+    c.decrypt(ct, pt)
+    c.decode(pt, zz)
+    err = np.abs(from_dev(zz, np.float64) - z).max()
+    assert err < noise_bound(P.n, P.scale), err
+    assert c.device_errors() == 0
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_add_bit_exact(name):
+    c = gpu_ctx(name)
+    P, sh, pk, zero = oracle_keys(name)
+    pt = _plaintexts(P, 2, 3)
+    a = np.stack([oracle.encrypt_zinc(P, zero, pt[0], 10)] * 2)
+    b = np.stack([oracle.encrypt_vanilla(P, pk, pt[1], 11), oracle.encrypt_zinc(P, zero, pt[1], 12)])
+    out = empty_u64(2, 2, P.L, P.n)
+    say(f"{name} add")
+    c.add(to_dev(a), to_dev(b), out)
+    got = from_dev(out)
+    for i in range(2):
+        assert np.array_equal(got[i], oracle.add(P, a[i], b[i]))
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_ciphertext_independent_of_batch_position(scheme):
+    c = gpu_ctx("n8192")
+    P = oracle_keys("n8192")[0]
+    z = make_slots(W_MAIN, 9)
+    idv = list(range(500, 509))
+    big = empty_u64(9, 2, P.L, P.n)
+    one = empty_u64(1, 2, P.L, P.n)
+    say(f"batch invariance scheme={scheme}")
+    c.encrypt_slots(scheme, to_dev(z), ids(idv), big)
+    c.encrypt_slots(scheme, to_dev(z[4:5]), ids(idv[4:5]), one)
+    assert np.array_equal(from_dev(big)[4], from_dev(one)[0])
+    again = empty_u64(9, 2, P.L, P.n)
+    c.encrypt_slots(scheme, to_dev(z), ids(idv), again)          # repeat run: deterministic
+    assert np.array_equal(from_dev(big), from_dev(again))
+
+
+def test_state_and_range_errors():
+    torch_cuda()
+    ps = PARAM_SETS["n4096"]
+    c = zinc.context_for(ps)
+    z = to_dev(np.zeros((1, ps.slots)))
+    ct = empty_u64(1, 2, ps.limbs, ps.n)
+    pt = empty_u64(1, ps.limbs, ps.n)
+    with pytest.raises(zinc.ZincError) as e:
+        c.encrypt_slots(zinc.ZINC_SCHEME_VANILLA, z, ids([0]), ct)
+    assert e.value.status == zinc.ZINC_E_STATE
+    with pytest.raises(zinc.ZincError) as e:
+        c.precompute()
+    assert e.value.status == zinc.ZINC_E_STATE
+    c.keygen()
+    with pytest.raises(zinc.ZincError) as e:
+        c.encrypt(pt, ids([0]), ct)
+    assert e.value.status == zinc.ZINC_E_STATE
+    c.precompute()
+    with pytest.raises(zinc.ZincError) as e:
+        c.encode(to_dev(np.zeros((1, ps.slots + 1))), pt)
+    assert e.value.status == zinc.ZINC_E_RANGE
+    with pytest.raises(zinc.ZincError) as e:
+        c.encrypt_slots(7, z, ids([0]), ct)
+    assert e.value.status == zinc.ZINC_E_INVAL
+    # a slot value whose scaled magnitude reaches 2^62 sets the device flag
+    assert c.device_errors() == 0
+    huge = np.full((1, ps.slots), 2.0 ** 40)       # coefficient 0 = Delta * 2^40 = 2^65
+    huge[0, 1] = np.nan
+    say("range flag")
+    c.encode(to_dev(huge), pt)
+    assert c.device_errors() & 1
+    assert c.device_errors() == 0          # read-and-clear
+    c.close()
+
+
+def _check_fused_against_oracle(name, w, picks, scheme):
+    """Full-size batch in the launch configuration the benchmark times; sampled
+    ciphertexts checked one by one against the oracle: c2 bit-exact, c1 equal
+    up to NTT(delta) with delta in {-1, 0, 1} on the oracle's rounding-tie set
+    (the difference's inverse NTT is taken by the library's own INTT, which is
+    checked bit-exact above)."""
+    c = gpu_ctx(name)
+    P, sh, pk, zero = oracle_keys(name)
+    z = make_slots(w)
+    B = z.shape[0]
+    ct = empty_u64(B, 2, P.L, P.n)
+    say(f"{name} full batch B={B} scheme={scheme}")
+    c.encrypt_slots(scheme, to_dev(z), ids(range(B)), ct)
+    torch = torch_cuda()
+    sel = from_dev(ct[torch.tensor(picks, device="cuda")].contiguous())
+    got = {i: sel[k] for k, i in enumerate(picks)}
+    key = zero if scheme == zinc.ZINC_SCHEME_ZINC else pk
+    for i in picks:
+        want = oracle.encrypt_slots(P, scheme, key, z[i], i)
+        assert np.array_equal(got[i][1], want[1]), i
+        if np.array_equal(got[i][0], want[0]):
+            continue
+        m, fr = oracle.encode(P, z[i])
+        tie = np.abs(np.abs(fr) - 0.5) <= tie_tau(P.n, np.abs(m).max())
+        for l, q in enumerate(P.data_moduli):
+            diff = ((got[i][0, l].astype(object) - want[0, l].astype(object)) % q).astype(np.uint64)
+            d = to_dev(diff[None, :])
+            c.ntt_inverse(l, d)
+            delta = centred(from_dev(d)[0], q)
+            assert np.abs(delta).max() <= 1 and np.all(tie[delta != 0]), (i, l)
+    return got
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_full_batch_n8192_sampled(scheme):
+    _check_fused_against_oracle("n8192", W_MAIN, [0, 1, 511, 1023], scheme)
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_full_batch_n16384_sampled(scheme):
+    _check_fused_against_oracle("n16384", W_LARGE, [0, 4095], scheme)
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_full_batch_n4096(scheme):
+    _check_fused_against_oracle("n4096", W_SMALL, list(range(0, 64, 9)), scheme)

@@ -73,14 +73,19 @@ def test_cdt_matches_decimal_computation(orc):
 
 
 def test_ternary_distribution(orc):
-    x = orc.sample_ternary(0, 12345, orc.TAG_U, 300000)
+    x = orc.sample_ternary(0, 12345, orc.TAG_U, 300000)  # multiple of 4
     assert set(np.unique(x).tolist()) <= {-1, 0, 1}
     counts = np.array([(x == v).sum() for v in (-1, 0, 1)], dtype=float)
     exp = len(x) / 3
     chi2 = ((counts - exp) ** 2 / exp).sum()
     assert chi2 < 20.0   # 2 dof; p ~ 5e-5
-    # counter addressing: a prefix of a longer draw is the shorter draw
-    assert np.array_equal(orc.sample_ternary(0, 12345, orc.TAG_U, 1001), x[:1001])
+    # counter addressing: coefficient k of an n-draw uses word k // (n/4) of
+    # block k mod (n/4), so the first quarter of a 4n-draw is column 0 of the
+    # blocks; each quarter is itself a uniform ternary stream
+    q4 = len(x) // 4
+    for j in range(4):
+        cj = np.array([(x[j * q4:(j + 1) * q4] == v).sum() for v in (-1, 0, 1)], dtype=float)
+        assert ((cj - q4 / 3) ** 2 / (q4 / 3)).sum() < 20.0
 
 
 def _gauss_pmf():
@@ -104,7 +109,9 @@ def test_gaussian_distribution(orc):
     sel = exp > 20
     chi2 = (((counts - exp) ** 2 / exp)[sel]).sum()
     assert chi2 < sel.sum() + 8 * np.sqrt(2 * sel.sum())
-    assert np.array_equal(orc.sample_gaussian(0, 99, orc.TAG_E1, 777), x[:777])
+    # halves of one draw share Philox blocks but are separate 64-bit words
+    h = n // 2
+    assert abs(np.corrcoef(x[:h].astype(float), x[h:].astype(float))[0, 1]) < 0.005
 
 
 def test_gaussian_extreme_uniforms(orc):

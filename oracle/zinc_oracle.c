@@ -17,10 +17,12 @@
  *     with psi the smallest primitive 2N-th root of unity mod q.  [S]
  *   - Randomness: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), key = seed,
  *     counter = (block, tag | limb<<8, ct_id lo, ct_id hi).  [S]
- *   - Ternary R_2: x = floor(3 w / 2^32) - 1 from one 32-bit word.  [S]
+ *   - Ternary R_2: x = floor(3 w / 2^32) - 1 from one 32-bit word; coefficient
+ *     k uses word k/(N/4) of block k mod N/4.  [S]
  *   - chi (sigma = 3.2, Polynomials and Distributions): discrete Gaussian on
- *     [-19, 19] by cumulative-table inversion of one 64-bit uniform; the table
- *     is an input (computed by the Python side of the oracle).  [S]
+ *     [-19, 19] by cumulative-table inversion of one 64-bit uniform (half
+ *     k/(N/2) of block k mod N/2); the table is an input (computed by the
+ *     Python side of the oracle).  [S]
  *   - Encoding: canonical embedding with slot j <-> root zeta^(5^j mod 2N),
  *     zeta = exp(i pi / N), real slots, round half to even.  [S]
  */
@@ -228,23 +230,27 @@ static void philox_block(uint64_t seed, uint64_t ct_id, uint32_t tag, uint32_t l
     oracle_philox4x32_10(ctr, key, out);
 }
 
-/* R_2 (ternary, uniform on {-1,0,1}; Polynomials and Distributions). */
+/* R_2 (ternary, uniform on {-1,0,1}; Polynomials and Distributions).
+ * n is a multiple of 4; coefficient k takes word k / (n/4) of block k mod (n/4). */
 void oracle_sample_ternary(uint64_t seed, uint64_t ct_id, uint32_t tag, uint32_t n, int64_t* out) {
+    uint32_t quarter = n / 4;
     for (uint32_t k = 0; k < n; k++) {
         uint32_t w[4];
-        philox_block(seed, ct_id, tag, 0, k / 4, w);
-        uint64_t v = ((uint64_t)3 * w[k % 4]) >> 32;
+        philox_block(seed, ct_id, tag, 0, k % quarter, w);
+        uint64_t v = ((uint64_t)3 * w[k / quarter]) >> 32;
         out[k] = (int64_t)v - 1;
     }
 }
 
-/* chi: discrete Gaussian on [-19, 19]; x = -19 + #{i : U >= T[i]}. */
+/* chi: discrete Gaussian on [-19, 19]; x = -19 + #{i : U >= T[i]}.
+ * n is even; coefficient k takes the 64-bit half k / (n/2) of block k mod (n/2). */
 void oracle_sample_gaussian(uint64_t seed, uint64_t ct_id, uint32_t tag, uint32_t n,
                             const uint64_t cdt[38], int64_t* out) {
+    uint32_t half = n / 2;
     for (uint32_t k = 0; k < n; k++) {
         uint32_t w[4];
-        philox_block(seed, ct_id, tag, 0, k / 2, w);
-        uint32_t h = 2 * (k % 2);
+        philox_block(seed, ct_id, tag, 0, k % half, w);
+        uint32_t h = 2 * (k / half);
         uint64_t u = (uint64_t)w[h] | ((uint64_t)w[h + 1] << 32);
         int64_t cnt = 0;
         for (int i = 0; i < 38; i++) cnt += (u >= cdt[i]) ? 1 : 0;

@@ -22,15 +22,30 @@ sys.path.insert(0, ROOT)
 
 METRIC = "CKKS encryptions/sec (Zinc vs vanilla, same GPU) at N=8192; p99 latency served"
 
-# ALU roofline of the NTT butterfly (the dominant work of the fused launch).
+# ALU roofline of the NTT butterflies (the dominant work of the fused launch).
 # VALU issue rate of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.32e12
-# lane-cycles/s.  A 64-bit Shoup butterfly needs at least 10 multiply-class
-# instructions (hi(y*w') from four 32x32 partial products, two low 64-bit
-# products from three each), issued at a quarter of the full rate, plus 12
-# full-rate adds, compares and selects: 52 lane-cycles.
+# lane-cycles/s; integer multiplies (v_mad_u64_u32, v_mul_lo/hi_u32) and FP64
+# FMA all issue at the full rate on gfx950, so a butterfly costs its
+# instruction count.  The shortest butterfly per modulus class:
+#   q >= 2^50, 64-bit integer Cooley-Tukey with a Shoup twiddle and lazy
+#   (Harvey) reduction: 26 VALU ops (6 for hi64(y*w'), 4 + 4 for the two low
+#   64-bit products, 2 for their difference, 4 to subtract 2q from x when
+#   needed, 2 for x + t, 4 for x - t + 2q);
+#   q < 2^50, exact FP64 arithmetic: 8 VALU ops (mul + rint for the quotient,
+#   mul and FMA for the exact product, FMA for the remainder, add, and the
+#   butterfly's add and subtract).
+# The peak butterfly rate of a launch is the VALU rate over the mean cost of
+# its limbs' butterflies.
 VALU_LANE_CYCLES_PER_S = 256 * 4 * 16 * 2.4e9
-BFLY_LANE_CYCLES = 10 * 4 + 12
-PEAK_BFLY_PER_S = VALU_LANE_CYCLES_PER_S / BFLY_LANE_CYCLES
+BFLY_COST_INT = 26
+BFLY_COST_FP64 = 8
+
+
+def peak_bfly_per_s(limbs: int, fp64_mask: int) -> float:
+    cost = sum(BFLY_COST_FP64 if (fp64_mask >> l) & 1 else BFLY_COST_INT for l in range(limbs)) / limbs
+    return VALU_LANE_CYCLES_PER_S / cost
+
+
 HBM_PEAK_BYTES_PER_S = 8.0e12
 KERNEL_SOURCES = ("paper_2408_07304_amd/csrc/kernels.hip", "paper_2408_07304_amd/csrc/device.h")
 
@@ -81,12 +96,12 @@ def cpu_baseline(ws, scheme: int, budget_s: float):
     _, pk = oracle.keygen(P)
     key = oracle.zinc_precompute(P, pk) if scheme == 1 else pk
     threads = max(1, min(os.cpu_count() or 1, 16))
-    z = make_slots(ws, min(ws.batch, 4 * threads))
+    z1 = make_slots(ws, 1)
     t0 = time.perf_counter()
-    oracle.encrypt_slots(P, scheme, key, z[0], 0)
+    oracle.encrypt_slots(P, scheme, key, z1[0], 0)
     one = time.perf_counter() - t0
-    count = int(max(threads, min(len(z), threads * max(1, budget_s / max(one, 1e-6)))))
-    count = min(count, len(z))
+    count = int(min(ws.batch, max(threads, threads * budget_s / max(one, 1e-6))))
+    z = make_slots(ws, count)
     t0 = time.perf_counter()
     with cf.ThreadPoolExecutor(max_workers=threads) as ex:
         list(ex.map(lambda i: oracle.encrypt_slots(P, scheme, key, z[i], i), range(count)))
@@ -105,6 +120,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--scheme", choices=["both", "zinc", "vanilla"], default="both")
+    ap.add_argument("--copy-ref-mib", type=int, default=0,
+                    help="also run one torch copy of this many MiB (reference kernel for HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -156,6 +173,14 @@ def main():
         print(f"[bench] {name}: {res[name]}", file=sys.stderr, flush=True)
     if ctx.device_errors():
         raise SystemExit("device error flag set during the benchmark")
+    if args.copy_ref_mib:
+        src = torch.empty(args.copy_ref_mib << 17, dtype=torch.int64, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] copy reference: {args.copy_ref_mib} MiB read + {args.copy_ref_mib} MiB written",
+              file=sys.stderr, flush=True)
 
     main_name = run[0]
     sch = schemes[main_name]
@@ -163,6 +188,7 @@ def main():
     value = ws.batch / (r["ms_per_step"] / 1e3)
     bfly = ws.batch * butterflies(ps.n, ps.limbs, sch)
     achieved = bfly / (r["kernel_ms"] / 1e3)
+    peak = peak_bfly_per_s(ps.limbs, ctx.info()["ntt_fp64_mask"])
     line = {
         "metric": METRIC,
         "value": value,
@@ -179,8 +205,9 @@ def main():
         "config": {"workload": ws.name, "N": ps.n, "moduli_bits": list(ps.bits), "data_limbs": ps.limbs,
                    "scale_log2": int(math.log2(ps.scale)), "batch": ws.batch, "slots": ps.slots,
                    "slot_values": ws.dist, "scheme": main_name, "fused_encode": True},
-        "roofline": {"bound": "alu", "achieved": achieved / 1e9, "peak": PEAK_BFLY_PER_S / 1e9,
-                     "unit": "Gbutterfly/s", "frac": achieved / PEAK_BFLY_PER_S,
+        "roofline": {"bound": "alu", "achieved": achieved / 1e9, "peak": peak / 1e9,
+                     "unit": "Gbutterfly/s", "frac": achieved / peak,
+                     "ntt_fp64_limbs": [l for l in range(ps.limbs) if (ctx.info()["ntt_fp64_mask"] >> l) & 1],
                      "traffic": traffic_from_profile(ws.name, main_name),
                      "kernel": "k_encrypt (fused encode + sample + NTT + add)",
                      "kernel_ms": r["kernel_ms"], "butterflies_per_launch": bfly,

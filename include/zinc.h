@@ -115,6 +115,9 @@ typedef struct zinc_info {
     size_t ciphertext_bytes;    /* 2*L*N*8 per ciphertext                     */
     int keyed;                  /* zinc_keygen done                           */
     int precomputed;            /* zinc_precompute done                       */
+    uint32_t ntt_fp64_mask;     /* bit l set: limb l's forward NTT runs in exact
+                                   FP64 arithmetic (moduli below 2^50), else in
+                                   64-bit integer (Shoup) arithmetic          */
 } zinc_info;
 
 /* Create a context on the current HIP device: validate the parameters, derive

@@ -44,7 +44,7 @@ class zinc_info(ctypes.Structure):
                 ("psi", ctypes.c_uint64 * ZINC_MAX_MODULI), ("scale", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("cdt", ctypes.c_uint64 * 38),
                 ("plaintext_bytes", ctypes.c_size_t), ("ciphertext_bytes", ctypes.c_size_t),
-                ("keyed", ctypes.c_int), ("precomputed", ctypes.c_int)]
+                ("keyed", ctypes.c_int), ("precomputed", ctypes.c_int), ("ntt_fp64_mask", ctypes.c_uint32)]
 
 
 class zinc_item(ctypes.Structure):
@@ -183,7 +183,8 @@ class Context:
                 "moduli": [int(x) for x in i.moduli[:M]], "psi": [int(x) for x in i.psi[:M]],
                 "scale": i.scale, "seed": int(i.seed), "cdt": [int(x) for x in i.cdt],
                 "plaintext_bytes": int(i.plaintext_bytes), "ciphertext_bytes": int(i.ciphertext_bytes),
-                "keyed": bool(i.keyed), "precomputed": bool(i.precomputed)}
+                "keyed": bool(i.keyed), "precomputed": bool(i.precomputed),
+                "ntt_fp64_mask": int(i.ntt_fp64_mask)}
 
     # -- the scheme ---------------------------------------------------------
     def keygen(self, stream=None):

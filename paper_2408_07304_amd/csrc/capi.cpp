@@ -2,6 +2,7 @@
 // roots of unity, twiddle / FFT / sampler tables), the Gen -> precompute ->
 // Enc / Enc_z state machine and the argument checks of every entry point.
 #include <cmath>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -94,6 +95,10 @@ zinc_status zinc_ctx_create(const zinc_params* p, zinc_ctx** out) {
     const int logh = (int)p->log_n - 1;
     std::vector<LimbConst> limbs(M);
     std::vector<uint64_t> tw((size_t)M * n * 2), itw((size_t)M * n * 2);
+    std::vector<double> tw_fp((size_t)M * n * 2);
+    // ZINC_NTT_ARITH=int forces the integer path for every modulus.
+    const char* arith = std::getenv("ZINC_NTT_ARITH");
+    const bool force_int = arith && std::strcmp(arith, "int") == 0;
     std::vector<uint64_t> pw(n);
     for (uint32_t l = 0; l < M; ++l) {
         const uint64_t ql = q[l];
@@ -103,6 +108,10 @@ zinc_status zinc_ctx_create(const zinc_params* p, zinc_ctx** out) {
         limbs[l].ninv = powmod_host(n, ql - 2, ql);
         limbs[l].ninv_sh = shoup_companion(limbs[l].ninv, ql);
         limbs[l].half = (ql - 1) / 2;
+        limbs[l].qd = (double)ql;
+        limbs[l].qinv = (double)(1.0L / (long double)ql);
+        limbs[l].fp = force_int || ql >= kFpBound ? 0u : (ql >= kFpNoReduceBound ? 2u : 1u);
+        if (limbs[l].fp) c->fp64_mask |= 1u << l;
         for (int inv = 0; inv < 2; ++inv) {
             const uint64_t root = inv ? powmod_host(c->psi[l], ql - 2, ql) : c->psi[l];
             pw[0] = 1;
@@ -112,6 +121,10 @@ zinc_status zinc_ctx_create(const zinc_params* p, zinc_ctx** out) {
                 const uint64_t w = pw[bitrev(k, (int)p->log_n)];
                 dst[2 * k] = w;
                 dst[2 * k + 1] = shoup_companion(w, ql);
+                if (!inv && ql < kFpBound) {
+                    tw_fp[((size_t)l * n + k) * 2] = (double)w;
+                    tw_fp[((size_t)l * n + k) * 2 + 1] = (double)((long double)w / (long double)ql);
+                }
             }
         }
     }
@@ -141,7 +154,7 @@ zinc_status zinc_ctx_create(const zinc_params* p, zinc_ctx** out) {
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
     const size_t o_limbs = take(sizeof(LimbConst) * M);
-    const size_t o_tw = take(nb * 2 * M), o_itw = take(nb * 2 * M);
+    const size_t o_tw = take(nb * 2 * M), o_itw = take(nb * 2 * M), o_twfp = take(nb * 2 * M);
     const size_t o_fft = take(sizeof(double) * H), o_twist = take(sizeof(double) * 2 * H);
     const size_t o_pos = take(4 * H), o_cdt = take(8 * kCdtPad);
     const size_t o_sk = take(nb * M), o_sks = take(nb * M);
@@ -156,7 +169,8 @@ zinc_status zinc_ctx_create(const zinc_params* p, zinc_ctx** out) {
     c->d_block = base;
     struct Up { size_t o; const void* src; size_t bytes; } ups[] = {
         {o_limbs, limbs.data(), sizeof(LimbConst) * M}, {o_tw, tw.data(), nb * 2 * M},
-        {o_itw, itw.data(), nb * 2 * M}, {o_fft, fft_tw.data(), sizeof(double) * H},
+        {o_itw, itw.data(), nb * 2 * M}, {o_twfp, tw_fp.data(), nb * 2 * M},
+        {o_fft, fft_tw.data(), sizeof(double) * H},
         {o_twist, twist.data(), sizeof(double) * 2 * H}, {o_pos, slot_pos.data(), 4 * H},
         {o_cdt, cdt, 8 * kCdtPad}};
     for (const Up& u : ups) {
@@ -183,6 +197,7 @@ zinc_status zinc_ctx_create(const zinc_params* p, zinc_ctx** out) {
     d.limbs = reinterpret_cast<const LimbConst*>(base + o_limbs);
     d.tw = reinterpret_cast<const uint64_t*>(base + o_tw);
     d.itw = reinterpret_cast<const uint64_t*>(base + o_itw);
+    d.tw_fp = reinterpret_cast<const double*>(base + o_twfp);
     d.fft_tw = reinterpret_cast<const double*>(base + o_fft);
     d.twist = reinterpret_cast<const double*>(base + o_twist);
     d.slot_pos = reinterpret_cast<const uint32_t*>(base + o_pos);
@@ -223,6 +238,7 @@ zinc_status zinc_ctx_info(const zinc_ctx* c, zinc_info* o) {
     o->ciphertext_bytes = 2 * (size_t)c->L * c->n * 8;
     o->keyed = c->keyed;
     o->precomputed = c->precomputed;
+    o->ntt_fp64_mask = c->fp64_mask;
     return ZINC_OK;
 }
 

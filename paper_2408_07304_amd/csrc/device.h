@@ -119,6 +119,24 @@ __device__ __forceinline__ int gauss_from(u64 u, const u64* __restrict__ cdt) {
     return cnt - kTail;
 }
 
+// The same count by a branch-free binary search over the table padded to 64
+// entries with 2^64-1 (tab in LDS, ascending).  After the six steps pos is the
+// number of entries <= u, except that it stops at 63; the pads can only be
+// <= u when u = 2^64-1, where every real threshold is counted, so the count of
+// real thresholds is min(pos, 38).
+__device__ __forceinline__ int gauss_bsearch(u64 u, const u64* tab) {
+    uint32_t pos = 0;
+#pragma unroll
+    for (uint32_t step = 32; step >= 1; step >>= 1) pos += (u >= tab[pos + step - 1]) ? step : 0u;
+    return (int)(pos < (uint32_t)kCdtLen ? pos : (uint32_t)kCdtLen) - kTail;
+}
+
+// Copy the padded table into LDS (one entry per thread of the first 64).
+__device__ __forceinline__ void load_cdt(u64* tab, const u64* __restrict__ cdt, uint32_t t) {
+    if (t < (uint32_t)kCdtPad) tab[t] = cdt[t];
+    __syncthreads();
+}
+
 // R_2: x = floor(3 w / 2^32) - 1
 __device__ __forceinline__ int ternary_from(uint32_t w) { return (int)__umulhi(w, 3u) - 1; }
 
@@ -153,110 +171,254 @@ struct Geom {
     static_assert(LOGN / NPASS + (LOGN % NPASS ? 1 : 0) <= LOGR, "pass wider than a thread's registers");
 };
 
-// LDS address swizzle: XOR of the low four index bits with the next four,
-// which keeps every pass's access pattern free of bank conflicts.
-__device__ __forceinline__ uint32_t swz(uint32_t i) { return i ^ ((i >> 4) & 15u); }
+// LDS layout: one 8-byte pad word after every 16 words.  pad() is additive
+// over index parts with disjoint bits, so a thread's per-register addresses are
+// its base address plus compile-time offsets (instruction immediates), and the
+// strided access patterns of the passes spread over all banks.
+__host__ __device__ constexpr uint32_t pad(uint32_t i) { return i + (i >> 4); }
+template <int N>
+struct LdsWords { static constexpr int value = N + N / 16; };
+
+// An integer the compiler cannot see through: address arithmetic derived from
+// it is recomputed inside each transform instead of being hoisted out of the
+// per-limb loop and held in registers across it, and loads through different
+// instances are not merged.
+__device__ __forceinline__ uint32_t opaque_tid(uint32_t t) {
+    asm volatile("" : "+v"(t));
+    return t;
+}
+__device__ __forceinline__ uint32_t opaque_s(uint32_t x) {
+    asm volatile("" : "+s"(x));
+    return x;
+}
+
+// The part of thread t's index that selects twiddles in pass P.  Twiddle
+// indices drop every index bit below the butterfly's bit, so when the pass's
+// active bits lie above the 64 lane bits (LO >= 6) the twiddles are uniform
+// across the wavefront: the index is then taken from the first lane, which puts
+// it in scalar registers and turns the twiddle loads into scalar loads.
+template <class G, int P>
+__device__ __forceinline__ uint32_t tw_tpart(uint32_t t) {
+    constexpr int LO = G::LO(P), HH = G::H(P);
+    if constexpr (P == 0) {
+        return 0u;
+    } else if constexpr (LO >= 6) {
+        return (uint32_t)__builtin_amdgcn_readfirstlane((int)(t >> LO)) << HH;
+    } else {
+        return G::tpart(P, t);
+    }
+}
+
+// Twiddle index of the butterfly on local bit b of register c in pass P.
+template <class G, int P>
+__device__ __forceinline__ uint32_t tw_index(uint32_t tp, int c, int b) {
+    constexpr int LO = G::LO(P), HH = G::H(P), K = G::K(P);
+    const int s = G::LOGN - HH + (K - 1 - b);          // global stage
+    return (1u << s) + ((tp | G::cpart(P, c)) >> (LO + b + 1));
+}
+
+template <class G, int P, class T>
+__device__ __forceinline__ void lds_put(T* lds, const T (&v)[G::R], uint32_t t) {
+    T* base = lds + pad(G::tpart(P, t));
+#pragma unroll
+    for (int c = 0; c < G::R; ++c) base[pad(G::cpart(P, c))] = v[c];
+}
+
+template <class G, int P, class T>
+__device__ __forceinline__ void lds_get(const T* lds, T (&v)[G::R], uint32_t t) {
+    const T* base = lds + pad(G::tpart(P, t));
+#pragma unroll
+    for (int c = 0; c < G::R; ++c) v[c] = base[pad(G::cpart(P, c))];
+}
+
+// ---- integer path (any modulus below 2^60): Shoup butterflies, [0, 4q) ----
 
 template <class G, int P>
-__device__ __forceinline__ void fwd_pass(u64 (&v)[G::R], uint32_t tp, const u64* __restrict__ tw,
-                                         u64 q, u64 q2) {
-    constexpr int K = G::K(P), LO = G::LO(P), HH = G::H(P);
+__device__ __forceinline__ void fwd_pass(u64 (&v)[G::R], uint32_t t, const u64* __restrict__ tw,
+                                         uint32_t toff, u64 q, u64 q2) {
+    constexpr int K = G::K(P);
+    const uint32_t tp = tw_tpart<G, P>(t);
 #pragma unroll
     for (int i = 0; i < K; ++i) {
-        const int b = K - 1 - i;                 // local bit of this stage
-        const int s = G::LOGN - HH + i;          // global stage index
+        const int b = K - 1 - i;
 #pragma unroll
         for (int c = 0; c < G::R; ++c) {
             if (c & (1 << b)) continue;
-            const uint32_t j = (P == 0 ? 0u : tp) | G::cpart(P, c);
-            const uint32_t ti = (1u << s) + (j >> (LO + b + 1));
-            ct_bfly(v[c], v[c | (1 << b)], tw[2 * ti], tw[2 * ti + 1], q, q2);
+            const uint32_t ti = toff + 2 * tw_index<G, P>(tp, c, b);
+            ct_bfly(v[c], v[c | (1 << b)], tw[ti], tw[ti + 1], q, q2);
         }
     }
 }
 
 template <class G, int P>
-__device__ __forceinline__ void inv_pass(u64 (&v)[G::R], uint32_t tp, const u64* __restrict__ itw,
-                                         u64 q, u64 q2) {
-    constexpr int K = G::K(P), LO = G::LO(P);
+__device__ __forceinline__ void inv_pass(u64 (&v)[G::R], uint32_t t, const u64* __restrict__ itw,
+                                         uint32_t toff, u64 q, u64 q2) {
+    constexpr int K = G::K(P);
+    const uint32_t tp = tw_tpart<G, P>(t);
 #pragma unroll
     for (int b = 0; b < K; ++b) {
-        const int s = G::LOGN - 1 - (LO + b);
 #pragma unroll
         for (int c = 0; c < G::R; ++c) {
             if (c & (1 << b)) continue;
-            const uint32_t j = (P == 0 ? 0u : tp) | G::cpart(P, c);
-            const uint32_t ti = (1u << s) + (j >> (LO + b + 1));
-            gs_bfly(v[c], v[c | (1 << b)], itw[2 * ti], itw[2 * ti + 1], q, q2);
+            const uint32_t ti = toff + 2 * tw_index<G, P>(tp, c, b);
+            gs_bfly(v[c], v[c | (1 << b)], itw[ti], itw[ti + 1], q, q2);
         }
     }
 }
 
 template <class G, int P>
-__device__ __forceinline__ void lds_put(u64* lds, const u64 (&v)[G::R], uint32_t t) {
-    const uint32_t tp = G::tpart(P, t);
-#pragma unroll
-    for (int c = 0; c < G::R; ++c) lds[swz(tp | G::cpart(P, c))] = v[c];
-}
-
-template <class G, int P>
-__device__ __forceinline__ void lds_get(const u64* lds, u64 (&v)[G::R], uint32_t t) {
-    const uint32_t tp = G::tpart(P, t);
-#pragma unroll
-    for (int c = 0; c < G::R; ++c) v[c] = lds[swz(tp | G::cpart(P, c))];
-}
-
-template <class G, int P>
-__device__ __forceinline__ void fwd_rest(u64 (&v)[G::R], u64* lds, const u64* __restrict__ tw, u64 q,
-                                         u64 q2, uint32_t t) {
+__device__ __forceinline__ void fwd_rest(u64 (&v)[G::R], u64* lds, const u64* __restrict__ tw, uint32_t toff,
+                                         u64 q, u64 q2, uint32_t t) {
     if constexpr (P < G::NPASS) {
         __syncthreads();
         lds_put<G, P - 1>(lds, v, t);
         __syncthreads();
         lds_get<G, P>(lds, v, t);
-        fwd_pass<G, P>(v, G::tpart(P, t), tw, q, q2);
-        fwd_rest<G, P + 1>(v, lds, tw, q, q2, t);
+        fwd_pass<G, P>(v, t, tw, toff, q, q2);
+        fwd_rest<G, P + 1>(v, lds, tw, toff, q, q2, t);
     }
 }
 
-// Forward NTT: v in pass-0 layout with values in [0, 4q) -> v in the last
-// pass's layout with values in [0, 4q).  Uses lds[N] as exchange buffer.
+// Forward NTT modulo q of limb `limb`: v in pass-0 layout with values in
+// [0, 4q) -> v in the last pass's layout with values in [0, 4q).  tw is the
+// [M][N][2] table of (psi^brv(k), Shoup companion); lds the padded exchange
+// buffer.
 template <class G>
-__device__ __forceinline__ void ntt_fwd(u64 (&v)[G::R], u64* lds, const u64* __restrict__ tw, u64 q,
-                                        u64 q2, uint32_t t) {
-    fwd_pass<G, 0>(v, 0u, tw, q, q2);
-    fwd_rest<G, 1>(v, lds, tw, q, q2, t);
+__device__ __forceinline__ void ntt_fwd(u64 (&v)[G::R], u64* lds, const u64* __restrict__ tw, uint32_t limb,
+                                        u64 q, u64 q2, uint32_t t_) {
+    const uint32_t toff = opaque_s(limb * 2u * G::N);
+    const uint32_t t = opaque_tid(t_);
+    fwd_pass<G, 0>(v, t, tw, toff, q, q2);
+    fwd_rest<G, 1>(v, lds, tw, toff, q, q2, t);
 }
 
 template <class G, int P>
-__device__ __forceinline__ void inv_rest(u64 (&v)[G::R], u64* lds, const u64* __restrict__ itw, u64 q,
-                                         u64 q2, uint32_t t) {
+__device__ __forceinline__ void inv_rest(u64 (&v)[G::R], u64* lds, const u64* __restrict__ itw, uint32_t toff,
+                                         u64 q, u64 q2, uint32_t t) {
     if constexpr (P >= 0) {
         __syncthreads();
         lds_put<G, P + 1>(lds, v, t);
         __syncthreads();
         lds_get<G, P>(lds, v, t);
-        inv_pass<G, P>(v, G::tpart(P, t), itw, q, q2);
-        inv_rest<G, P - 1>(v, lds, itw, q, q2, t);
+        inv_pass<G, P>(v, t, itw, toff, q, q2);
+        inv_rest<G, P - 1>(v, lds, itw, toff, q, q2, t);
     }
 }
 
 // Inverse NTT without the N^-1 factor: v in the last pass's layout with values
 // in [0, 2q) -> v in pass-0 layout with values in [0, 2q).
 template <class G>
-__device__ __forceinline__ void ntt_inv(u64 (&v)[G::R], u64* lds, const u64* __restrict__ itw, u64 q,
-                                        u64 q2, uint32_t t) {
+__device__ __forceinline__ void ntt_inv(u64 (&v)[G::R], u64* lds, const u64* __restrict__ itw, uint32_t limb,
+                                        u64 q, u64 q2, uint32_t t_) {
     constexpr int PL = G::NPASS - 1;
-    inv_pass<G, PL>(v, G::tpart(PL, t), itw, q, q2);
-    inv_rest<G, PL - 1>(v, lds, itw, q, q2, t);
+    const uint32_t toff = opaque_s(limb * 2u * G::N);
+    const uint32_t t = opaque_tid(t_);
+    inv_pass<G, PL>(v, t, itw, toff, q, q2);
+    inv_rest<G, PL - 1>(v, lds, itw, toff, q, q2, t);
 }
 
-// Write v (last forward pass layout) to LDS so that lds[swz(i)] is coefficient i.
-template <class G>
-__device__ __forceinline__ void to_natural(u64* lds, const u64 (&v)[G::R], uint32_t t) {
+// Write v (last forward pass layout) to LDS so that lds[pad(i)] is coefficient i.
+template <class G, class T>
+__device__ __forceinline__ void to_natural(T* lds, const T (&v)[G::R], uint32_t t_) {
+    const uint32_t t = opaque_tid(t_);
     __syncthreads();
     lds_put<G, G::NPASS - 1>(lds, v, t);
     __syncthreads();
+}
+
+// ---- FP64 path (moduli below 2^50): exact integer arithmetic in doubles ----
+//
+// MI355X issues FP64 FMA at the full VALU rate, so for moduli below 2^50 the
+// butterfly runs on doubles holding exact signed integers.  With w < q and the
+// rounded quotient wq = fl(w/q), for |y| < 2^53:
+//   k = rint(y * wq), h = fl(y w), l = fma(y, w, -h) = y w - h exactly,
+//   r = fma(-k, q, h) = h - k q exactly (|h - k q| < 2^53), t = r + l exactly,
+// so t = y w - k q with |t| <= q (1/2 + |y| 2^-52).  Values are not reduced
+// between stages: from |x| <= q they stay below 20 q over 15 stages, which is
+// below 2^52 for q < 2^47.  Moduli in [2^47, 2^50) are rounded into
+// [-q/2, q/2] at the start of every pass (at most five stages), which keeps
+// them below 2^52 as well.
+
+#pragma clang fp contract(off)
+__device__ __forceinline__ double fp_mulmod(double y, double w, double wq, double q) {
+    const double k = __builtin_rint(y * wq);
+    const double h = y * w;
+    const double l = __builtin_fma(y, w, -h);
+    const double r = __builtin_fma(-k, q, h);
+    return r + l;
+}
+
+__device__ __forceinline__ void ct_bfly_fp(double& x, double& y, double w, double wq, double q) {
+    const double t = fp_mulmod(y, w, wq, q);
+    const double a = x;
+    x = a + t;
+    y = a - t;
+}
+
+// x - round(x / q) q, exact for |x| < 2^53: result in [-q/2 - 1, q/2 + 1].
+__device__ __forceinline__ double fp_round_reduce(double x, double q, double qinv) {
+    return __builtin_fma(-__builtin_rint(x * qinv), q, x);
+}
+
+// exact integer in (-2^52, 2^52) -> canonical residue in [0, q) as uint64
+__device__ __forceinline__ u64 fp_canon(double x, double q, double qinv) {
+    double r = __builtin_fma(-__builtin_floor(x * qinv), q, x);   // [-q, 2q)
+    r = r < 0.0 ? r + q : r;
+    r = r >= q ? r - q : r;
+    return (u64)__double_as_longlong(r + 0x1p52) - 0x4330000000000000ull;
+}
+
+// uint64 below 2^52 -> double, exactly
+__device__ __forceinline__ double u64_to_fp(u64 x) {
+    return __longlong_as_double((long long)(x | 0x4330000000000000ull)) - 0x1p52;
+}
+#pragma clang fp contract(on)
+
+template <class G, int P>
+__device__ __forceinline__ void fwd_pass_fp(double (&v)[G::R], uint32_t t, const double* __restrict__ tw,
+                                            uint32_t toff, double q, double qinv, bool reduce) {
+    constexpr int K = G::K(P);
+    const uint32_t tp = tw_tpart<G, P>(t);
+    if (reduce) {
+#pragma unroll
+        for (int c = 0; c < G::R; ++c) v[c] = fp_round_reduce(v[c], q, qinv);
+    }
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const int b = K - 1 - i;
+#pragma unroll
+        for (int c = 0; c < G::R; ++c) {
+            if (c & (1 << b)) continue;
+            const uint32_t ti = toff + 2 * tw_index<G, P>(tp, c, b);
+            ct_bfly_fp(v[c], v[c | (1 << b)], tw[ti], tw[ti + 1], q);
+        }
+    }
+}
+
+template <class G, int P>
+__device__ __forceinline__ void fwd_rest_fp(double (&v)[G::R], double* lds, const double* __restrict__ tw,
+                                            uint32_t toff, double q, double qinv, bool reduce, uint32_t t) {
+    if constexpr (P < G::NPASS) {
+        __syncthreads();
+        lds_put<G, P - 1>(lds, v, t);
+        __syncthreads();
+        lds_get<G, P>(lds, v, t);
+        fwd_pass_fp<G, P>(v, t, tw, toff, q, qinv, reduce);
+        fwd_rest_fp<G, P + 1>(v, lds, tw, toff, q, qinv, reduce, t);
+    }
+}
+
+// Forward NTT in FP64: v in pass-0 layout, exact integers with |v| <= q ->
+// v in the last pass's layout, exact integers congruent to the transform, with
+// magnitude below 2^52.  tw_fp is the [M][N][2] table of (psi^brv(k), its
+// quotient by q) as doubles.
+template <class G>
+__device__ __forceinline__ void ntt_fwd_fp(double (&v)[G::R], double* lds, const double* __restrict__ tw,
+                                           uint32_t limb, double q, double qinv, bool reduce, uint32_t t_) {
+    const uint32_t toff = opaque_s(limb * 2u * G::N);
+    const uint32_t t = opaque_tid(t_);
+    fwd_pass_fp<G, 0>(v, t, tw, toff, q, qinv, false);
+    fwd_rest_fp<G, 1>(v, lds, tw, toff, q, qinv, reduce, t);
 }
 
 // ---------------------------------------------------------------------------
@@ -275,11 +437,20 @@ struct Packed8 {
     }
     __device__ __forceinline__ void set(int c, int x) { w[c >> 2] |= ((uint32_t)(x & 0xFF)) << (8 * (c & 3)); }
     __device__ __forceinline__ int get(int c) const { return (int)(int8_t)(uint8_t)(w[c >> 2] >> (8 * (c & 3))); }
+    // A copy whose words the compiler cannot see through, so that values
+    // derived from the samples (conversions, residues) are computed where they
+    // are used, not hoisted out of the per-limb loop and kept live.
+    __device__ __forceinline__ Packed8 fresh() const {
+        Packed8 r = *this;
+#pragma unroll
+        for (int i = 0; i < R / 4; ++i) asm volatile("" : "+v"(r.w[i]));
+        return r;
+    }
 };
 
 template <class G>
-__device__ __forceinline__ void sample_gauss_p0(Packed8<G::R>& out, const DevParams& p, u64 ct_id,
-                                                uint32_t tag, uint32_t t) {
+__device__ __forceinline__ void sample_gauss_p0(Packed8<G::R>& out, const DevParams& p, const u64* tab,
+                                                u64 ct_id, uint32_t tag, uint32_t t) {
     constexpr int TOP = 1 << (G::K(0) - 1);
     const uint32_t tp = G::tpart(0, t);
     out.clear();
@@ -288,8 +459,8 @@ __device__ __forceinline__ void sample_gauss_p0(Packed8<G::R>& out, const DevPar
         if (c & TOP) continue;
         const uint32_t k = tp | G::cpart(0, c);   // < N/2
         const U4 r = draw(p.seed, ct_id, tag, 0, k);
-        out.set(c, gauss_from((u64)r.x | ((u64)r.y << 32), p.cdt));
-        out.set(c | TOP, gauss_from((u64)r.z | ((u64)r.w << 32), p.cdt));
+        out.set(c, gauss_bsearch((u64)r.x | ((u64)r.y << 32), tab));
+        out.set(c | TOP, gauss_bsearch((u64)r.z | ((u64)r.w << 32), tab));
     }
 }
 

@@ -31,120 +31,193 @@ struct EncArgs {
     u64* ct;                 // [batch][2][L][N]
 };
 
-// Epilogue: lds holds the NTT output (values in [0, 4q)) in natural order;
-// out[i] = (ntt[i] + add[i]) mod q with add canonical.
+// Per-limb view of the arithmetic: the forward NTT runs either on uint64
+// residues (Shoup, any modulus) or on doubles holding exact integers (moduli
+// below 2^50); after to_natural() the transform's coefficient k is read back as
+// a canonical residue with canon(k).
 template <class G>
-__device__ __forceinline__ void store_plus(const u64* lds, const u64* __restrict__ add, u64* __restrict__ out,
-                                           u64 q, u64 q2, uint32_t t) {
-#pragma unroll
-    for (int i = 0; i < G::R; ++i) {
-        const uint32_t k = t + G::T * i;
-        out[k] = addmod(canon4(lds[swz(k)], q, q2), add[k], q);
-    }
-}
+struct LimbNtt {
+    const u64* tw;
+    const double* tw_fp;
+    u64 q, q2;
+    double qd, qinv;
+    uint32_t mode;
+    uint32_t limb;
+    u64* lds;
+    uint32_t t;
 
+    __device__ __forceinline__ LimbNtt(const DevParams& p, const LimbConst& lc, uint32_t l, u64* lds_, uint32_t t_)
+        : tw(p.tw), tw_fp(p.tw_fp), q(lc.q), q2(lc.q2), qd(lc.qd), qinv(lc.qinv), mode(lc.fp), limb(l),
+          lds(lds_), t(t_) {}
+
+    __device__ __forceinline__ bool fp() const { return mode != 0; }
+
+    // Transform the pass-0 inputs given by in(c) (integer path: a residue in
+    // [0, 2q); FP path: an exact integer of magnitude at most q, as double).
+    template <class InInt, class InFp>
+    __device__ __forceinline__ void run(InInt in_int, InFp in_fp) const {
+        if (fp()) {
+            double v[G::R];
+#pragma unroll
+            for (int c = 0; c < G::R; ++c) v[c] = in_fp(c);
+            double* ld = reinterpret_cast<double*>(lds);
+            ntt_fwd_fp<G>(v, ld, tw_fp, limb, qd, qinv, mode == 2, t);
+            to_natural<G>(ld, v, t);
+        } else {
+            u64 v[G::R];
+#pragma unroll
+            for (int c = 0; c < G::R; ++c) v[c] = in_int(c);
+            ntt_fwd<G>(v, lds, tw, limb, q, q2, t);
+            to_natural<G>(lds, v, t);
+        }
+    }
+
+    // canonical residue of transform coefficient k (after run())
+    __device__ __forceinline__ u64 canon(uint32_t k) const {
+        if (fp()) return fp_canon(reinterpret_cast<const double*>(lds)[pad(k)], qd, qinv);
+        return canon4(lds[pad(k)], q, q2);
+    }
+
+    // a * b mod q for canonical residues a, b (the pk * u_hat product)
+    __device__ __forceinline__ u64 mul(u64 a, u64 b, u64 b_sh) const {
+        if (fp()) {
+            const double bd = u64_to_fp(b);
+            const double r = fp_mulmod(u64_to_fp(a), bd, bd * qinv, qd);   // |r| < q
+            return (u64)__double_as_longlong((r < 0.0 ? r + qd : r) + 0x1p52) - 0x4330000000000000ull;
+        }
+        return csub(shoup_lazy(a, b, b_sh, q), q);
+    }
+};
+
+// Pass-0 message input of limb l: (m + e) with m read back from the stash
+// (encoded slots) or from the caller's plaintext residues.
+template <class G, bool FROM_SLOTS>
+struct MessageIn {
+    const long long* stash;
+    const u64* pt;
+    Packed8<G::R> e;
+    LimbConst lc;
+    uint32_t tp0;
+    __device__ __forceinline__ u64 ri(int c) const {       // residue in [0, 2q)
+        const uint32_t k = tp0 | G::cpart(0, c);
+        if constexpr (FROM_SLOTS) return reduce_signed(stash[k] + e.get(c), lc);
+        else return pt[k] + small_mod(e.get(c), lc.q);
+    }
+    __device__ __forceinline__ double rf(int c) const {    // |value| <= q
+        const uint32_t k = tp0 | G::cpart(0, c);
+        if constexpr (FROM_SLOTS) return u64_to_fp(reduce_signed(stash[k] + e.get(c), lc));
+        else return u64_to_fp(pt[k]) + (double)e.get(c);
+    }
+};
+
+// One workgroup per ciphertext.  The encoded message (FROM_SLOTS) is stashed
+// as int64 in the ciphertext's own c1 slot of the last limb, in pass-0 layout;
+// each thread reads back only what it wrote, and the slot is overwritten only
+// by that limb's c1 epilogue, after the last read.  Vanilla keeps NTT(u) of the
+// current limb in that limb's c2 slot the same way until c2 is stored.
 template <int LOGN, int SCHEME, bool FROM_SLOTS>
-__global__ void __launch_bounds__(Cfg<LOGN>::G::T) k_encrypt(DevParams p, EncArgs a) {
+__global__ void __launch_bounds__(Cfg<LOGN>::G::T) __attribute__((amdgpu_waves_per_eu(4)))
+k_encrypt(DevParams p, EncArgs a) {
     using G = typename Cfg<LOGN>::G;
-    constexpr int R = G::R, N = G::N;
-    __shared__ u64 lds[N];
+    constexpr int R = G::R, N = G::N, T = G::T;
+    __shared__ u64 lds[LdsWords<N>::value];
+    __shared__ u64 tab[kCdtPad];
     const uint32_t t = threadIdx.x;
     const uint32_t b = blockIdx.x;
     const u64 ct_id = a.ct_ids[b];
+    load_cdt(tab, p.cdt, t);
     const uint32_t L = p.L;
     u64* ct = a.ct + (size_t)b * 2 * L * N;
+    long long* stash = reinterpret_cast<long long*>(ct + (size_t)(L - 1) * N);
+    const u64* pt = a.pt + (size_t)b * L * N;
 
-    long long m[R];
     if constexpr (FROM_SLOTS) {
+        long long m[R];
         encode_p0<G>(m, lds, p, a.slots + (size_t)b * a.n_slots, a.n_slots, t);
+        const uint32_t tp0 = G::tpart(0, t);
+#pragma unroll
+        for (int c = 0; c < R; ++c) stash[tp0 | G::cpart(0, c)] = m[c];
     }
-    const uint32_t tp0 = G::tpart(0, t);
-    u64 v[R];
 
     if constexpr (SCHEME == ZINC_SCHEME_ZINC) {
         Packed8<R> e1, e2;
-        sample_gauss_p0<G>(e1, p, ct_id, TAG_E1Z, t);
-        sample_gauss_p0<G>(e2, p, ct_id, TAG_E2Z, t);
+        sample_gauss_p0<G>(e1, p, tab, ct_id, TAG_E1Z, t);
+        sample_gauss_p0<G>(e2, p, tab, ct_id, TAG_E2Z, t);
 #pragma unroll 1
         for (uint32_t l = 0; l < L; ++l) {
             const LimbConst lc = p.limbs[l];
-            const u64* tw = p.tw + (size_t)l * 2 * N;
+            const LimbNtt<G> nt{p, lc, l, lds, t};
+            const MessageIn<G, FROM_SLOTS> msg{stash, pt + (size_t)l * N, e1.fresh(), lc, G::tpart(0, opaque_tid(t))};
             // c1 = zero1 + NTT(m + e1')
+            nt.run([&](int c) { return msg.ri(c); }, [&](int c) { return msg.rf(c); });
+            {
+                const uint32_t tt = opaque_tid(t);
+                const u64* z = p.zero + (size_t)l * N;
+                u64* out = ct + (size_t)l * N;
 #pragma unroll
-            for (int c = 0; c < R; ++c) {
-                if constexpr (FROM_SLOTS) {
-                    v[c] = reduce_signed(m[c] + e1.get(c), lc);
-                } else {
-                    const u64 x = a.pt[((size_t)b * L + l) * N + (tp0 | G::cpart(0, c))];
-                    v[c] = x + small_mod(e1.get(c), lc.q);      // [0, 2q)
+                for (int i = 0; i < R; ++i) {
+                    const uint32_t k = tt + T * i;
+                    out[k] = addmod(nt.canon(k), z[k], lc.q);
                 }
             }
-            ntt_fwd<G>(v, lds, tw, lc.q, lc.q2, t);
-            to_natural<G>(lds, v, t);
-            store_plus<G>(lds, p.zero + (size_t)l * N, ct + (size_t)l * N, lc.q, lc.q2, t);
             // c2 = zero2 + NTT(e2')
+            const Packed8<R> e2l = e2.fresh();
+            nt.run([&](int c) { return small_mod(e2l.get(c), lc.q); }, [&](int c) { return (double)e2l.get(c); });
+            {
+                const uint32_t tt = opaque_tid(t);
+                const u64* z = p.zero + (size_t)(L + l) * N;
+                u64* out = ct + (size_t)(L + l) * N;
 #pragma unroll
-            for (int c = 0; c < R; ++c) v[c] = small_mod(e2.get(c), lc.q);
-            ntt_fwd<G>(v, lds, tw, lc.q, lc.q2, t);
-            to_natural<G>(lds, v, t);
-            store_plus<G>(lds, p.zero + (size_t)(L + l) * N, ct + (size_t)(L + l) * N, lc.q, lc.q2, t);
+                for (int i = 0; i < R; ++i) {
+                    const uint32_t k = tt + T * i;
+                    out[k] = addmod(nt.canon(k), z[k], lc.q);
+                }
+            }
         }
     } else {
         Packed8<R> u, e1, e2;
         sample_ternary_p0<G>(u, p, ct_id, TAG_U, t);
-        sample_gauss_p0<G>(e1, p, ct_id, TAG_E1, t);
-        sample_gauss_p0<G>(e2, p, ct_id, TAG_E2, t);
+        sample_gauss_p0<G>(e1, p, tab, ct_id, TAG_E1, t);
+        sample_gauss_p0<G>(e2, p, tab, ct_id, TAG_E2, t);
         const uint32_t M = p.M;
 #pragma unroll 1
         for (uint32_t l = 0; l < L; ++l) {
             const LimbConst lc = p.limbs[l];
-            const u64 q = lc.q, q2 = lc.q2;
-            const u64* tw = p.tw + (size_t)l * 2 * N;
-            // u_hat, kept in natural order (coefficients t + T i)
-#pragma unroll
-            for (int c = 0; c < R; ++c) v[c] = small_mod(u.get(c), q);
-            ntt_fwd<G>(v, lds, tw, q, q2, t);
-            to_natural<G>(lds, v, t);
-            u64 uh[R];
-#pragma unroll
-            for (int i = 0; i < R; ++i) uh[i] = canon4(lds[swz(t + G::T * i)], q, q2);
-            // c2 = pk2 u_hat + NTT(e2)
-#pragma unroll
-            for (int c = 0; c < R; ++c) v[c] = small_mod(e2.get(c), q);
-            ntt_fwd<G>(v, lds, tw, q, q2, t);
-            to_natural<G>(lds, v, t);
+            const LimbNtt<G> nt{p, lc, l, lds, t};
+            u64* c1 = ct + (size_t)l * N;
+            u64* c2 = ct + (size_t)(L + l) * N;
+            // u_hat -> the c2 slot of this limb (natural order)
+            const Packed8<R> ul = u.fresh();
+            nt.run([&](int c) { return small_mod(ul.get(c), lc.q); }, [&](int c) { return (double)ul.get(c); });
             {
-                const u64* pk = p.pk + (size_t)(M + l) * N;
-                const u64* pks = p.pk_sh + (size_t)(M + l) * N;
-                u64* out = ct + (size_t)(L + l) * N;
+                const uint32_t tt = opaque_tid(t);
 #pragma unroll
-                for (int i = 0; i < R; ++i) {
-                    const uint32_t k = t + G::T * i;
-                    const u64 pu = csub(shoup_lazy(uh[i], pk[k], pks[k], q), q);
-                    out[k] = addmod(canon4(lds[swz(k)], q, q2), pu, q);
-                }
+                for (int i = 0; i < R; ++i) c2[tt + T * i] = nt.canon(tt + T * i);
             }
             // c1 = pk1 u_hat + NTT(m + e1)
-#pragma unroll
-            for (int c = 0; c < R; ++c) {
-                if constexpr (FROM_SLOTS) {
-                    v[c] = reduce_signed(m[c] + e1.get(c), lc);
-                } else {
-                    const u64 x = a.pt[((size_t)b * L + l) * N + (tp0 | G::cpart(0, c))];
-                    v[c] = x + small_mod(e1.get(c), q);
-                }
-            }
-            ntt_fwd<G>(v, lds, tw, q, q2, t);
-            to_natural<G>(lds, v, t);
+            const MessageIn<G, FROM_SLOTS> msg{stash, pt + (size_t)l * N, e1.fresh(), lc, G::tpart(0, opaque_tid(t))};
+            nt.run([&](int c) { return msg.ri(c); }, [&](int c) { return msg.rf(c); });
             {
+                const uint32_t tt = opaque_tid(t);
                 const u64* pk = p.pk + (size_t)l * N;
                 const u64* pks = p.pk_sh + (size_t)l * N;
-                u64* out = ct + (size_t)l * N;
 #pragma unroll
                 for (int i = 0; i < R; ++i) {
-                    const uint32_t k = t + G::T * i;
-                    const u64 pu = csub(shoup_lazy(uh[i], pk[k], pks[k], q), q);
-                    out[k] = addmod(canon4(lds[swz(k)], q, q2), pu, q);
+                    const uint32_t k = tt + T * i;
+                    c1[k] = addmod(nt.canon(k), nt.mul(c2[k], pk[k], pks[k]), lc.q);
+                }
+            }
+            // c2 = pk2 u_hat + NTT(e2)
+            const Packed8<R> e2l = e2.fresh();
+            nt.run([&](int c) { return small_mod(e2l.get(c), lc.q); }, [&](int c) { return (double)e2l.get(c); });
+            {
+                const uint32_t tt = opaque_tid(t);
+                const u64* pk = p.pk + (size_t)(M + l) * N;
+                const u64* pks = p.pk_sh + (size_t)(M + l) * N;
+#pragma unroll
+                for (int i = 0; i < R; ++i) {
+                    const uint32_t k = tt + T * i;
+                    c2[k] = addmod(nt.canon(k), nt.mul(c2[k], pk[k], pks[k]), lc.q);
                 }
             }
         }
@@ -159,39 +232,40 @@ __global__ void __launch_bounds__(Cfg<LOGN>::G::T) k_keygen(DevParams p, u64* sk
                                                               u64* pk_sh) {
     using G = typename Cfg<LOGN>::G;
     constexpr int R = G::R, N = G::N;
-    __shared__ u64 lds[N];
+    __shared__ u64 lds[LdsWords<N>::value];
+    __shared__ u64 tab[kCdtPad];
     const uint32_t t = threadIdx.x;
     const uint32_t l = blockIdx.x;
+    load_cdt(tab, p.cdt, t);
     const LimbConst lc = p.limbs[l];
     const u64 q = lc.q, q2 = lc.q2;
-    const u64* tw = p.tw + (size_t)l * 2 * N;
     const uint32_t M = p.M;
 
     Packed8<R> s, e;
     sample_ternary_p0<G>(s, p, ZINC_KEY_ID, TAG_SK, t);
-    sample_gauss_p0<G>(e, p, ZINC_KEY_ID, TAG_EPK, t);
+    sample_gauss_p0<G>(e, p, tab, ZINC_KEY_ID, TAG_EPK, t);
     u64 v[R];
 #pragma unroll
     for (int c = 0; c < R; ++c) v[c] = small_mod(s.get(c), q);
-    ntt_fwd<G>(v, lds, tw, q, q2, t);
+    ntt_fwd<G>(v, lds, p.tw, l, q, q2, t);
     to_natural<G>(lds, v, t);
     u64 sh[R], shs[R];
 #pragma unroll
     for (int i = 0; i < R; ++i) {
         const uint32_t k = t + G::T * i;
-        sh[i] = canon4(lds[swz(k)], q, q2);
+        sh[i] = canon4(lds[pad(k)], q, q2);
         shs[i] = shoup_companion_dev(sh[i], q);
         sk[(size_t)l * N + k] = sh[i];
         sk_sh[(size_t)l * N + k] = shs[i];
     }
 #pragma unroll
     for (int c = 0; c < R; ++c) v[c] = small_mod(e.get(c), q);
-    ntt_fwd<G>(v, lds, tw, q, q2, t);
+    ntt_fwd<G>(v, lds, p.tw, l, q, q2, t);
     to_natural<G>(lds, v, t);
 #pragma unroll
     for (int i = 0; i < R; ++i) {
         const uint32_t k = t + G::T * i;
-        const u64 eh = canon4(lds[swz(k)], q, q2);
+        const u64 eh = canon4(lds[pad(k)], q, q2);
         // a <- R_q, drawn directly in the NTT domain: 128 uniform bits mod q
         const U4 r = draw(p.seed, ZINC_KEY_ID, TAG_A, l, k);
         const u64 hi = ((u64)r.w << 32) | r.z, lo = ((u64)r.y << 32) | r.x;
@@ -213,7 +287,7 @@ __global__ void __launch_bounds__(Cfg<LOGN>::G::T) k_encode(DevParams p, const d
                                                               uint32_t n_slots, u64* pt) {
     using G = typename Cfg<LOGN>::G;
     constexpr int R = G::R, N = G::N;
-    __shared__ u64 lds[N];
+    __shared__ u64 lds[LdsWords<N>::value];
     const uint32_t t = threadIdx.x, b = blockIdx.x;
     long long m[R];
     encode_p0<G>(m, lds, p, slots + (size_t)b * n_slots, n_slots, t);
@@ -233,7 +307,7 @@ template <int LOGN>
 __global__ void __launch_bounds__(Cfg<LOGN>::G::T) k_decrypt(DevParams p, const u64* ct, u64* pt) {
     using G = typename Cfg<LOGN>::G;
     constexpr int R = G::R, N = G::N, PL = G::NPASS - 1;
-    __shared__ u64 lds[N];
+    __shared__ u64 lds[LdsWords<N>::value];
     const uint32_t t = threadIdx.x, l = blockIdx.x, b = blockIdx.y, L = p.L;
     const LimbConst lc = p.limbs[l];
     const u64 q = lc.q, q2 = lc.q2;
@@ -244,12 +318,12 @@ __global__ void __launch_bounds__(Cfg<LOGN>::G::T) k_decrypt(DevParams p, const 
 #pragma unroll
     for (int i = 0; i < R; ++i) {
         const uint32_t k = t + G::T * i;
-        lds[swz(k)] = csub(c1[k] + csub(shoup_lazy(c2[k], s[k], ss[k], q), q), q2);   // [0, 2q)
+        lds[pad(k)] = csub(c1[k] + csub(shoup_lazy(c2[k], s[k], ss[k], q), q), q2);   // [0, 2q)
     }
     __syncthreads();
     u64 v[R];
     lds_get<G, PL>(lds, v, t);
-    ntt_inv<G>(v, lds, p.itw + (size_t)l * 2 * N, q, q2, t);
+    ntt_inv<G>(v, lds, p.itw, l, q, q2, t);
     u64* out = pt + ((size_t)b * L + l) * N;
     const uint32_t tp0 = G::tpart(0, t);
 #pragma unroll
@@ -263,7 +337,7 @@ template <int LOGN>
 __global__ void __launch_bounds__(Cfg<LOGN>::G::T) k_decode(DevParams p, const u64* pt, double* slots) {
     using G = typename Cfg<LOGN>::G;
     constexpr int N = G::N, H = N / 2, LOGH = LOGN - 1, T = G::T;
-    __shared__ u64 lds[N];
+    __shared__ u64 lds[LdsWords<N>::value];
     C2* A = reinterpret_cast<C2*>(lds);
     const uint32_t t = threadIdx.x, b = blockIdx.x, L = p.L;
     const LimbConst l0 = p.limbs[0];
@@ -319,26 +393,25 @@ template <int LOGN, bool INV>
 __global__ void __launch_bounds__(Cfg<LOGN>::G::T) k_ntt(DevParams p, uint32_t limb, u64* poly) {
     using G = typename Cfg<LOGN>::G;
     constexpr int R = G::R, N = G::N, PL = G::NPASS - 1;
-    __shared__ u64 lds[N];
+    __shared__ u64 lds[LdsWords<N>::value];
     const uint32_t t = threadIdx.x;
     u64* x = poly + (size_t)blockIdx.x * N;
     const LimbConst lc = p.limbs[limb];
     const u64 q = lc.q, q2 = lc.q2;
     const uint32_t tp0 = G::tpart(0, t);
-    u64 v[R];
     if constexpr (!INV) {
+        // the same per-modulus arithmetic as the encryption kernels
+        const LimbNtt<G> nt{p, lc, limb, lds, t};
+        nt.run([&](int c) { return x[tp0 | G::cpart(0, c)]; }, [&](int c) { return u64_to_fp(x[tp0 | G::cpart(0, c)]); });
 #pragma unroll
-        for (int c = 0; c < R; ++c) v[c] = x[tp0 | G::cpart(0, c)];
-        ntt_fwd<G>(v, lds, p.tw + (size_t)limb * 2 * N, q, q2, t);
-        to_natural<G>(lds, v, t);
-#pragma unroll
-        for (int i = 0; i < R; ++i) x[t + G::T * i] = canon4(lds[swz(t + G::T * i)], q, q2);
+        for (int i = 0; i < R; ++i) x[t + G::T * i] = nt.canon(t + G::T * i);
     } else {
+        u64 v[R];
 #pragma unroll
-        for (int i = 0; i < R; ++i) lds[swz(t + G::T * i)] = x[t + G::T * i];
+        for (int i = 0; i < R; ++i) lds[pad(t + G::T * i)] = x[t + G::T * i];
         __syncthreads();
         lds_get<G, PL>(lds, v, t);
-        ntt_inv<G>(v, lds, p.itw + (size_t)limb * 2 * N, q, q2, t);
+        ntt_inv<G>(v, lds, p.itw, limb, q, q2, t);
 #pragma unroll
         for (int c = 0; c < R; ++c) x[tp0 | G::cpart(0, c)] = csub(shoup_lazy(v[c], lc.ninv, lc.ninv_sh, q), q);
     }

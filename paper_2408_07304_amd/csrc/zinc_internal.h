@@ -25,7 +25,15 @@ struct LimbConst {
     uint64_t ninv;      // N^-1 mod q
     uint64_t ninv_sh;   // Shoup companion of N^-1
     uint64_t half;      // (q - 1) / 2, centred-lift threshold
+    double qd;          // q as a double (exact)
+    double qinv;        // 1/q rounded to double
+    uint32_t fp;        // forward-NTT arithmetic: 0 integer (Shoup), 1 FP64, 2 FP64 with per-pass rounding
+    uint32_t reserved;
 };
+
+// FP64 arithmetic is used for moduli below these bounds (see device.h).
+constexpr uint64_t kFpNoReduceBound = 1ull << 47;
+constexpr uint64_t kFpBound = 1ull << 50;
 
 // Everything a kernel needs about one parameter set, as device pointers.
 struct DevParams {
@@ -35,6 +43,7 @@ struct DevParams {
     const LimbConst* limbs;       // [M]
     const uint64_t* tw;           // [M][N][2]  (psi^brv(k), Shoup companion)
     const uint64_t* itw;          // [M][N][2]  (psi^-brv(k), Shoup companion)
+    const double* tw_fp;          // [M][N][2]  (psi^brv(k), psi^brv(k) / q) as doubles
     const double* fft_tw;         // [N/4][2]   exp(-2 pi i k / (N/2)), k < N/4
     const double* twist;          // [N/2][2]   exp(-i pi k / N),       k < N/2
     const uint32_t* slot_pos;     // [N/2]      brv_{log N - 1}((5^j mod 2N - 1) / 4)
@@ -57,6 +66,7 @@ struct zinc_ctx {
     uint64_t q[ZINC_MAX_MODULI] = {};
     uint64_t psi[ZINC_MAX_MODULI] = {};
     uint64_t cdt[zinc::kCdtLen] = {};
+    uint32_t fp64_mask = 0;       // limbs whose forward NTT uses FP64 arithmetic
     bool keyed = false, precomputed = false;
     // device allocations owned by the context
     void* d_block = nullptr;      // one allocation holding every table and key

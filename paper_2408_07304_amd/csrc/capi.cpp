@@ -45,8 +45,8 @@ const char* zinc_last_error(void) { return g_last_error.c_str(); }
 zinc_status zinc_ctx_create(const zinc_params* p, zinc_ctx** out) {
     if (!p || !out) return fail(ZINC_E_INVAL, "zinc_ctx_create: null argument");
     *out = nullptr;
-    if (p->log_n < 12 || p->log_n > 14)
-        return fail(ZINC_E_PARAM, "log_n must be 12, 13 or 14 (ring degree 4096..16384)");
+    if (p->log_n < 12 || p->log_n > 15)
+        return fail(ZINC_E_PARAM, "log_n must be in [12, 15] (ring degree 4096..32768)");
     if (p->n_moduli < 2 || p->n_moduli > ZINC_MAX_MODULI)
         return fail(ZINC_E_PARAM, "n_moduli must be in [2, 32] (data limbs plus the special prime)");
     if (!(p->scale > 0.0) || !std::isfinite(p->scale) || p->scale >= 4611686018427387904.0)

@@ -210,11 +210,15 @@ __device__ __forceinline__ uint32_t tw_tpart(uint32_t t) {
 }
 
 // Twiddle index of the butterfly on local bit b of register c in pass P.
+// For a whole transform (smul = 1) it is 2^s + g for stage s and group g.  A
+// transform of 2N coefficients whose first stage has been applied splits into
+// two independent N-point transforms (the halves h = 0, 1); their stage s and
+// group g use index (2 + h) 2^s + g of the 2N-point table (smul = 2 + h).
 template <class G, int P>
-__device__ __forceinline__ uint32_t tw_index(uint32_t tp, int c, int b) {
+__device__ __forceinline__ uint32_t tw_index(uint32_t tp, int c, int b, uint32_t smul) {
     constexpr int LO = G::LO(P), HH = G::H(P), K = G::K(P);
-    const int s = G::LOGN - HH + (K - 1 - b);          // global stage
-    return (1u << s) + ((tp | G::cpart(P, c)) >> (LO + b + 1));
+    const int s = G::LOGN - HH + (K - 1 - b);          // stage within this transform
+    return (smul << s) + ((tp | G::cpart(P, c)) >> (LO + b + 1));
 }
 
 template <class G, int P, class T>
@@ -235,7 +239,7 @@ __device__ __forceinline__ void lds_get(const T* lds, T (&v)[G::R], uint32_t t) 
 
 template <class G, int P>
 __device__ __forceinline__ void fwd_pass(u64 (&v)[G::R], uint32_t t, const u64* __restrict__ tw,
-                                         uint32_t toff, u64 q, u64 q2) {
+                                         uint32_t toff, uint32_t smul, u64 q, u64 q2) {
     constexpr int K = G::K(P);
     const uint32_t tp = tw_tpart<G, P>(t);
 #pragma unroll
@@ -244,7 +248,7 @@ __device__ __forceinline__ void fwd_pass(u64 (&v)[G::R], uint32_t t, const u64* 
 #pragma unroll
         for (int c = 0; c < G::R; ++c) {
             if (c & (1 << b)) continue;
-            const uint32_t ti = toff + 2 * tw_index<G, P>(tp, c, b);
+            const uint32_t ti = toff + 2 * tw_index<G, P>(tp, c, b, smul);
             ct_bfly(v[c], v[c | (1 << b)], tw[ti], tw[ti + 1], q, q2);
         }
     }
@@ -252,7 +256,7 @@ __device__ __forceinline__ void fwd_pass(u64 (&v)[G::R], uint32_t t, const u64* 
 
 template <class G, int P>
 __device__ __forceinline__ void inv_pass(u64 (&v)[G::R], uint32_t t, const u64* __restrict__ itw,
-                                         uint32_t toff, u64 q, u64 q2) {
+                                         uint32_t toff, uint32_t smul, u64 q, u64 q2) {
     constexpr int K = G::K(P);
     const uint32_t tp = tw_tpart<G, P>(t);
 #pragma unroll
@@ -260,7 +264,7 @@ __device__ __forceinline__ void inv_pass(u64 (&v)[G::R], uint32_t t, const u64* 
 #pragma unroll
         for (int c = 0; c < G::R; ++c) {
             if (c & (1 << b)) continue;
-            const uint32_t ti = toff + 2 * tw_index<G, P>(tp, c, b);
+            const uint32_t ti = toff + 2 * tw_index<G, P>(tp, c, b, smul);
             gs_bfly(v[c], v[c | (1 << b)], itw[ti], itw[ti + 1], q, q2);
         }
     }
@@ -268,53 +272,55 @@ __device__ __forceinline__ void inv_pass(u64 (&v)[G::R], uint32_t t, const u64* 
 
 template <class G, int P>
 __device__ __forceinline__ void fwd_rest(u64 (&v)[G::R], u64* lds, const u64* __restrict__ tw, uint32_t toff,
-                                         u64 q, u64 q2, uint32_t t) {
+                                         uint32_t smul, u64 q, u64 q2, uint32_t t) {
     if constexpr (P < G::NPASS) {
         __syncthreads();
         lds_put<G, P - 1>(lds, v, t);
         __syncthreads();
         lds_get<G, P>(lds, v, t);
-        fwd_pass<G, P>(v, t, tw, toff, q, q2);
-        fwd_rest<G, P + 1>(v, lds, tw, toff, q, q2, t);
+        fwd_pass<G, P>(v, t, tw, toff, smul, q, q2);
+        fwd_rest<G, P + 1>(v, lds, tw, toff, smul, q, q2, t);
     }
 }
 
 // Forward NTT modulo q of limb `limb`: v in pass-0 layout with values in
 // [0, 4q) -> v in the last pass's layout with values in [0, 4q).  tw is the
-// [M][N][2] table of (psi^brv(k), Shoup companion); lds the padded exchange
-// buffer.
+// [M][NT][2] table of (psi^brv(k), Shoup companion) of NT-point transforms
+// (NT = G::N, or 2 G::N for a half of a split transform, smul = 2 + half);
+// lds the padded exchange buffer.
 template <class G>
 __device__ __forceinline__ void ntt_fwd(u64 (&v)[G::R], u64* lds, const u64* __restrict__ tw, uint32_t limb,
-                                        u64 q, u64 q2, uint32_t t_) {
-    const uint32_t toff = opaque_s(limb * 2u * G::N);
+                                        u64 q, u64 q2, uint32_t t_, uint32_t smul = 1, uint32_t nt = G::N) {
+    const uint32_t toff = opaque_s(limb * 2u * nt);
     const uint32_t t = opaque_tid(t_);
-    fwd_pass<G, 0>(v, t, tw, toff, q, q2);
-    fwd_rest<G, 1>(v, lds, tw, toff, q, q2, t);
+    fwd_pass<G, 0>(v, t, tw, toff, smul, q, q2);
+    fwd_rest<G, 1>(v, lds, tw, toff, smul, q, q2, t);
 }
 
 template <class G, int P>
 __device__ __forceinline__ void inv_rest(u64 (&v)[G::R], u64* lds, const u64* __restrict__ itw, uint32_t toff,
-                                         u64 q, u64 q2, uint32_t t) {
+                                         uint32_t smul, u64 q, u64 q2, uint32_t t) {
     if constexpr (P >= 0) {
         __syncthreads();
         lds_put<G, P + 1>(lds, v, t);
         __syncthreads();
         lds_get<G, P>(lds, v, t);
-        inv_pass<G, P>(v, t, itw, toff, q, q2);
-        inv_rest<G, P - 1>(v, lds, itw, toff, q, q2, t);
+        inv_pass<G, P>(v, t, itw, toff, smul, q, q2);
+        inv_rest<G, P - 1>(v, lds, itw, toff, smul, q, q2, t);
     }
 }
 
 // Inverse NTT without the N^-1 factor: v in the last pass's layout with values
-// in [0, 2q) -> v in pass-0 layout with values in [0, 2q).
+// in [0, 2q) -> v in pass-0 layout with values in [0, 2q).  Table indexing as
+// for ntt_fwd.
 template <class G>
 __device__ __forceinline__ void ntt_inv(u64 (&v)[G::R], u64* lds, const u64* __restrict__ itw, uint32_t limb,
-                                        u64 q, u64 q2, uint32_t t_) {
+                                        u64 q, u64 q2, uint32_t t_, uint32_t smul = 1, uint32_t nt = G::N) {
     constexpr int PL = G::NPASS - 1;
-    const uint32_t toff = opaque_s(limb * 2u * G::N);
+    const uint32_t toff = opaque_s(limb * 2u * nt);
     const uint32_t t = opaque_tid(t_);
-    inv_pass<G, PL>(v, t, itw, toff, q, q2);
-    inv_rest<G, PL - 1>(v, lds, itw, toff, q, q2, t);
+    inv_pass<G, PL>(v, t, itw, toff, smul, q, q2);
+    inv_rest<G, PL - 1>(v, lds, itw, toff, smul, q, q2, t);
 }
 
 // Write v (last forward pass layout) to LDS so that lds[pad(i)] is coefficient i.
@@ -376,7 +382,7 @@ __device__ __forceinline__ double u64_to_fp(u64 x) {
 
 template <class G, int P>
 __device__ __forceinline__ void fwd_pass_fp(double (&v)[G::R], uint32_t t, const double* __restrict__ tw,
-                                            uint32_t toff, double q, double qinv, bool reduce) {
+                                            uint32_t toff, uint32_t smul, double q, double qinv, bool reduce) {
     constexpr int K = G::K(P);
     const uint32_t tp = tw_tpart<G, P>(t);
     if (reduce) {
@@ -389,7 +395,7 @@ __device__ __forceinline__ void fwd_pass_fp(double (&v)[G::R], uint32_t t, const
 #pragma unroll
         for (int c = 0; c < G::R; ++c) {
             if (c & (1 << b)) continue;
-            const uint32_t ti = toff + 2 * tw_index<G, P>(tp, c, b);
+            const uint32_t ti = toff + 2 * tw_index<G, P>(tp, c, b, smul);
             ct_bfly_fp(v[c], v[c | (1 << b)], tw[ti], tw[ti + 1], q);
         }
     }
@@ -397,28 +403,30 @@ __device__ __forceinline__ void fwd_pass_fp(double (&v)[G::R], uint32_t t, const
 
 template <class G, int P>
 __device__ __forceinline__ void fwd_rest_fp(double (&v)[G::R], double* lds, const double* __restrict__ tw,
-                                            uint32_t toff, double q, double qinv, bool reduce, uint32_t t) {
+                                            uint32_t toff, uint32_t smul, double q, double qinv, bool reduce,
+                                            uint32_t t) {
     if constexpr (P < G::NPASS) {
         __syncthreads();
         lds_put<G, P - 1>(lds, v, t);
         __syncthreads();
         lds_get<G, P>(lds, v, t);
-        fwd_pass_fp<G, P>(v, t, tw, toff, q, qinv, reduce);
-        fwd_rest_fp<G, P + 1>(v, lds, tw, toff, q, qinv, reduce, t);
+        fwd_pass_fp<G, P>(v, t, tw, toff, smul, q, qinv, reduce);
+        fwd_rest_fp<G, P + 1>(v, lds, tw, toff, smul, q, qinv, reduce, t);
     }
 }
 
 // Forward NTT in FP64: v in pass-0 layout, exact integers with |v| <= q ->
 // v in the last pass's layout, exact integers congruent to the transform, with
-// magnitude below 2^52.  tw_fp is the [M][N][2] table of (psi^brv(k), its
-// quotient by q) as doubles.
+// magnitude below 2^52.  tw_fp is the [M][NT][2] table of (psi^brv(k), its
+// quotient by q) as doubles; table indexing as for ntt_fwd.
 template <class G>
 __device__ __forceinline__ void ntt_fwd_fp(double (&v)[G::R], double* lds, const double* __restrict__ tw,
-                                           uint32_t limb, double q, double qinv, bool reduce, uint32_t t_) {
-    const uint32_t toff = opaque_s(limb * 2u * G::N);
+                                           uint32_t limb, double q, double qinv, bool reduce, uint32_t t_,
+                                           uint32_t smul = 1, uint32_t nt = G::N) {
+    const uint32_t toff = opaque_s(limb * 2u * nt);
     const uint32_t t = opaque_tid(t_);
-    fwd_pass_fp<G, 0>(v, t, tw, toff, q, qinv, false);
-    fwd_rest_fp<G, 1>(v, lds, tw, toff, q, qinv, reduce, t);
+    fwd_pass_fp<G, 0>(v, t, tw, toff, smul, q, qinv, false);
+    fwd_rest_fp<G, 1>(v, lds, tw, toff, smul, q, qinv, reduce, t);
 }
 
 // ---------------------------------------------------------------------------
@@ -494,7 +502,9 @@ struct C2 {
 
 __device__ __forceinline__ C2 cmul(C2 a, C2 b) { return C2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
 
-template <int LOGH, int T, int SIGN>
+// fft_tw holds exp(-2 pi i k / 2^LOGTAB) for k < 2^(LOGTAB-1); an FFT of
+// 2^LOGH <= 2^LOGTAB points reads it with stride 2^(LOGTAB-LOGH).
+template <int LOGH, int T, int SIGN, int LOGTAB = LOGH>
 __device__ __forceinline__ void fft_dit(C2* A, const double* __restrict__ fft_tw, uint32_t t) {
     constexpr int H = 1 << LOGH;
 #pragma unroll 1
@@ -503,7 +513,7 @@ __device__ __forceinline__ void fft_dit(C2* A, const double* __restrict__ fft_tw
         for (int b = t; b < H / 2; b += T) {
             const int pos = b & (half - 1);
             const int i0 = ((b >> (s - 1)) << s) + pos, i1 = i0 + half;
-            const int ti = pos << (LOGH - s);
+            const int ti = pos << (LOGTAB - s);
             C2 w{fft_tw[2 * ti], fft_tw[2 * ti + 1]};
             if (SIGN > 0) w.y = -w.y;
             const C2 a = A[i0], bw = cmul(A[i1], w);

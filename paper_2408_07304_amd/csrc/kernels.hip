@@ -6,7 +6,7 @@
 // into registers, encodes its slot vector once (FP64 FFT in LDS), and then
 // runs every limb's NTTs through one LDS exchange buffer, adding the cached
 // Enc(0) (Zinc) or pk * NTT(u) (vanilla) in the coalesced store epilogue.
-#include "device.h"
+#include "kernels_common.h"
 
 namespace zinc {
 
@@ -23,93 +23,6 @@ struct Cfg<14> { using G = Geom<14, 10>; };
 // ---------------------------------------------------------------------------
 // encryption
 // ---------------------------------------------------------------------------
-struct EncArgs {
-    const double* slots;     // [batch][n_slots] (FROM_SLOTS)
-    uint32_t n_slots;
-    const u64* pt;           // [batch][L][N]   (!FROM_SLOTS)
-    const u64* ct_ids;       // [batch]
-    u64* ct;                 // [batch][2][L][N]
-};
-
-// Per-limb view of the arithmetic: the forward NTT runs either on uint64
-// residues (Shoup, any modulus) or on doubles holding exact integers (moduli
-// below 2^50); after to_natural() the transform's coefficient k is read back as
-// a canonical residue with canon(k).
-template <class G>
-struct LimbNtt {
-    const u64* tw;
-    const double* tw_fp;
-    u64 q, q2;
-    double qd, qinv;
-    uint32_t mode;
-    uint32_t limb;
-    u64* lds;
-    uint32_t t;
-
-    __device__ __forceinline__ LimbNtt(const DevParams& p, const LimbConst& lc, uint32_t l, u64* lds_, uint32_t t_)
-        : tw(p.tw), tw_fp(p.tw_fp), q(lc.q), q2(lc.q2), qd(lc.qd), qinv(lc.qinv), mode(lc.fp), limb(l),
-          lds(lds_), t(t_) {}
-
-    __device__ __forceinline__ bool fp() const { return mode != 0; }
-
-    // Transform the pass-0 inputs given by in(c) (integer path: a residue in
-    // [0, 2q); FP path: an exact integer of magnitude at most q, as double).
-    template <class InInt, class InFp>
-    __device__ __forceinline__ void run(InInt in_int, InFp in_fp) const {
-        if (fp()) {
-            double v[G::R];
-#pragma unroll
-            for (int c = 0; c < G::R; ++c) v[c] = in_fp(c);
-            double* ld = reinterpret_cast<double*>(lds);
-            ntt_fwd_fp<G>(v, ld, tw_fp, limb, qd, qinv, mode == 2, t);
-            to_natural<G>(ld, v, t);
-        } else {
-            u64 v[G::R];
-#pragma unroll
-            for (int c = 0; c < G::R; ++c) v[c] = in_int(c);
-            ntt_fwd<G>(v, lds, tw, limb, q, q2, t);
-            to_natural<G>(lds, v, t);
-        }
-    }
-
-    // canonical residue of transform coefficient k (after run())
-    __device__ __forceinline__ u64 canon(uint32_t k) const {
-        if (fp()) return fp_canon(reinterpret_cast<const double*>(lds)[pad(k)], qd, qinv);
-        return canon4(lds[pad(k)], q, q2);
-    }
-
-    // a * b mod q for canonical residues a, b (the pk * u_hat product)
-    __device__ __forceinline__ u64 mul(u64 a, u64 b, u64 b_sh) const {
-        if (fp()) {
-            const double bd = u64_to_fp(b);
-            const double r = fp_mulmod(u64_to_fp(a), bd, bd * qinv, qd);   // |r| < q
-            return (u64)__double_as_longlong((r < 0.0 ? r + qd : r) + 0x1p52) - 0x4330000000000000ull;
-        }
-        return csub(shoup_lazy(a, b, b_sh, q), q);
-    }
-};
-
-// Pass-0 message input of limb l: (m + e) with m read back from the stash
-// (encoded slots) or from the caller's plaintext residues.
-template <class G, bool FROM_SLOTS>
-struct MessageIn {
-    const long long* stash;
-    const u64* pt;
-    Packed8<G::R> e;
-    LimbConst lc;
-    uint32_t tp0;
-    __device__ __forceinline__ u64 ri(int c) const {       // residue in [0, 2q)
-        const uint32_t k = tp0 | G::cpart(0, c);
-        if constexpr (FROM_SLOTS) return reduce_signed(stash[k] + e.get(c), lc);
-        else return pt[k] + small_mod(e.get(c), lc.q);
-    }
-    __device__ __forceinline__ double rf(int c) const {    // |value| <= q
-        const uint32_t k = tp0 | G::cpart(0, c);
-        if constexpr (FROM_SLOTS) return u64_to_fp(reduce_signed(stash[k] + e.get(c), lc));
-        else return u64_to_fp(pt[k]) + (double)e.get(c);
-    }
-};
-
 // One workgroup per ciphertext.  The encoded message (FROM_SLOTS) is stashed
 // as int64 in the ciphertext's own c1 slot of the last limb, in pass-0 layout;
 // each thread reads back only what it wrote, and the slot is overwritten only
@@ -452,6 +365,7 @@ __global__ void __launch_bounds__(256) k_sample(DevParams p, int kind, uint32_t 
 
 hipError_t launch_keygen(const DevParams& p, uint64_t* sk, uint64_t* sk_sh, uint64_t* pk,
                          uint64_t* pk_sh, hipStream_t s) {
+    if (p.log_n == 15) return launch_split_keygen(p, sk, sk_sh, pk, pk_sh, s);
 #define F(LN) hipLaunchKernelGGL(k_keygen<LN>, dim3(p.M), dim3(Cfg<LN>::G::T), 0, s, p, \
                                  (u64*)sk, (u64*)sk_sh, (u64*)pk, (u64*)pk_sh)
     ZINC_DISPATCH_LOGN(p.log_n, F)
@@ -461,6 +375,7 @@ hipError_t launch_keygen(const DevParams& p, uint64_t* sk, uint64_t* sk_sh, uint
 
 hipError_t launch_encrypt_pt(const DevParams& p, int scheme, const uint64_t* pt, uint32_t batch,
                              const uint64_t* ct_ids, uint64_t* ct, hipStream_t s) {
+    if (p.log_n == 15) return launch_split_encrypt(p, scheme, false, nullptr, 0, pt, batch, ct_ids, ct, s);
     EncArgs a{nullptr, 0, (const u64*)pt, (const u64*)ct_ids, (u64*)ct};
 #define F(LN)                                                                                          \
     if (scheme == ZINC_SCHEME_ZINC)                                                                    \
@@ -476,6 +391,8 @@ hipError_t launch_encrypt_pt(const DevParams& p, int scheme, const uint64_t* pt,
 
 hipError_t launch_encrypt_slots(const DevParams& p, int scheme, const double* slots, uint32_t n_slots,
                                 uint32_t batch, const uint64_t* ct_ids, uint64_t* ct, hipStream_t s) {
+    if (p.log_n == 15)
+        return launch_split_encrypt(p, scheme, true, slots, n_slots, nullptr, batch, ct_ids, ct, s);
     EncArgs a{slots, n_slots, nullptr, (const u64*)ct_ids, (u64*)ct};
 #define F(LN)                                                                                         \
     if (scheme == ZINC_SCHEME_ZINC)                                                                   \
@@ -491,6 +408,7 @@ hipError_t launch_encrypt_slots(const DevParams& p, int scheme, const double* sl
 
 hipError_t launch_encode(const DevParams& p, const double* slots, uint32_t n_slots, uint32_t batch,
                          uint64_t* pt, hipStream_t s) {
+    if (p.log_n == 15) return launch_split_encode(p, slots, n_slots, batch, pt, s);
 #define F(LN) hipLaunchKernelGGL(k_encode<LN>, dim3(batch), dim3(Cfg<LN>::G::T), 0, s, p, slots, n_slots, \
                                  (u64*)pt)
     ZINC_DISPATCH_LOGN(p.log_n, F)
@@ -500,6 +418,7 @@ hipError_t launch_encode(const DevParams& p, const double* slots, uint32_t n_slo
 
 hipError_t launch_decrypt(const DevParams& p, const uint64_t* ct, uint32_t batch, uint64_t* pt,
                           hipStream_t s) {
+    if (p.log_n == 15) return launch_split_decrypt(p, ct, batch, pt, s);
 #define F(LN) hipLaunchKernelGGL(k_decrypt<LN>, dim3(p.L, batch), dim3(Cfg<LN>::G::T), 0, s, p, \
                                  (const u64*)ct, (u64*)pt)
     ZINC_DISPATCH_LOGN(p.log_n, F)
@@ -509,6 +428,7 @@ hipError_t launch_decrypt(const DevParams& p, const uint64_t* ct, uint32_t batch
 
 hipError_t launch_decode(const DevParams& p, const uint64_t* pt, uint32_t batch, double* slots,
                          hipStream_t s) {
+    if (p.log_n == 15) return launch_split_decode(p, pt, batch, slots, s);
 #define F(LN) hipLaunchKernelGGL(k_decode<LN>, dim3(batch), dim3(Cfg<LN>::G::T), 0, s, p, (const u64*)pt, slots)
     ZINC_DISPATCH_LOGN(p.log_n, F)
 #undef F
@@ -529,6 +449,7 @@ hipError_t launch_add(const DevParams& p, const uint64_t* a, const uint64_t* b, 
 
 hipError_t launch_ntt(const DevParams& p, bool inverse, uint32_t limb, uint64_t* poly, uint32_t n_polys,
                       hipStream_t s) {
+    if (p.log_n == 15) return launch_split_ntt(p, inverse, limb, poly, n_polys, s);
 #define F(LN)                                                                                          \
     if (inverse)                                                                                       \
         hipLaunchKernelGGL((k_ntt<LN, true>), dim3(n_polys), dim3(Cfg<LN>::G::T), 0, s, p, limb, (u64*)poly); \

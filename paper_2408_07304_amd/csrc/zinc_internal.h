@@ -107,4 +107,19 @@ hipError_t launch_ntt(const DevParams& p, bool inverse, uint32_t limb, uint64_t*
 hipError_t launch_sample(const DevParams& p, int kind, uint32_t tag, uint32_t limb,
                          const uint64_t* ct_ids, uint32_t batch, void* out, hipStream_t s);
 
+// ring degree 32768 (kernels_split.hip)
+hipError_t launch_split_keygen(const DevParams& p, uint64_t* sk, uint64_t* sk_sh, uint64_t* pk,
+                               uint64_t* pk_sh, hipStream_t s);
+hipError_t launch_split_encrypt(const DevParams& p, int scheme, bool from_slots, const double* slots,
+                                uint32_t n_slots, const uint64_t* pt, uint32_t batch,
+                                const uint64_t* ct_ids, uint64_t* ct, hipStream_t s);
+hipError_t launch_split_encode(const DevParams& p, const double* slots, uint32_t n_slots,
+                               uint32_t batch, uint64_t* pt, hipStream_t s);
+hipError_t launch_split_decrypt(const DevParams& p, const uint64_t* ct, uint32_t batch,
+                                uint64_t* pt, hipStream_t s);
+hipError_t launch_split_decode(const DevParams& p, const uint64_t* pt, uint32_t batch,
+                               double* slots, hipStream_t s);
+hipError_t launch_split_ntt(const DevParams& p, bool inverse, uint32_t limb, uint64_t* poly,
+                            uint32_t n_polys, hipStream_t s);
+
 }  // namespace zinc

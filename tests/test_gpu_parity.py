@@ -12,11 +12,11 @@ import pytest
 import oracle
 import paper_2408_07304_amd as zinc
 from gpu_util import empty_u64, from_dev, gpu_ctx, ids, oracle_keys, to_dev, torch_cuda
-from paper_2408_07304_amd.workloads import PARAM_SETS, W_LARGE, W_MAIN, W_SMALL, make_slots
+from paper_2408_07304_amd.workloads import PARAM_SETS, W_LARGE, W_MAIN, W_MIXED, W_SMALL, make_slots
 
 pytestmark = pytest.mark.gpu
 
-NAMES = ["n4096", "n8192", "n16384"]
+NAMES = ["n4096", "n8192", "n16384", "n32768"]
 SCHEMES = [zinc.ZINC_SCHEME_VANILLA, zinc.ZINC_SCHEME_ZINC]
 
 
@@ -146,8 +146,8 @@ def test_encrypt_from_plaintext_bit_exact(name, scheme):
 def test_encode_within_tie_window(name):
     c = gpu_ctx(name)
     P = oracle_keys(name)[0]
-    w = {"n4096": W_SMALL, "n8192": W_MAIN, "n16384": W_LARGE}[name]
-    z = make_slots(w, 3)
+    w = {"n4096": W_SMALL, "n8192": W_MAIN, "n16384": W_LARGE, "n32768": W_MIXED}[name]
+    z = make_slots(w, 3, PARAM_SETS[name])
     z[2, 100:] = 0.0                                     # also a partly empty vector
     out = empty_u64(3, P.L, P.n)
     say(f"{name} encode")

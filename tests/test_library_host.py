@@ -54,6 +54,7 @@ def _params(log_n=13, bits=(60, 40, 40, 60), scale=2.0 ** 40, sigma=3.2, moduli=
 @pytest.mark.parametrize("kw,code", [
     (dict(log_n=11), zinc.ZINC_E_PARAM),
     (dict(log_n=16), zinc.ZINC_E_PARAM),
+    (dict(log_n=15, bits=(55,) * 40), zinc.ZINC_E_PARAM),                         # more than 32 moduli
     (dict(bits=(60,)), zinc.ZINC_E_PARAM),
     (dict(bits=(61, 40, 60)), zinc.ZINC_E_PARAM),
     (dict(bits=(10, 40, 60)), zinc.ZINC_E_PARAM),

@@ -111,6 +111,50 @@ def cpu_baseline(ws, scheme: int, budget_s: float):
                       f"{'Zinc' if scheme == 1 else 'vanilla'} encrypt), {threads} threads, {dt:.1f} s"}
 
 
+def bench_mixed(steps: int, warmup: int) -> dict:
+    """The mixed batch: 2048 plaintexts, ring degree drawn per plaintext from
+    {4096, 8192, 16384, 32768}, encrypted by one persistent plan launch
+    (captured as a HIP graph on the first launch, replayed after)."""
+    import torch
+
+    import paper_2408_07304_amd as zinc
+    from paper_2408_07304_amd.workloads import W_MIXED, make_mixed
+
+    ctxs = []
+    for ps in W_MIXED.params:
+        c = zinc.context_for(ps)
+        c.keygen()
+        c.precompute()
+        ctxs.append(c)
+    mb = make_mixed(W_MIXED)
+    items = list(zip(mb.ctx_idx.tolist(), mb.slot_off.tolist(), mb.ct_off.tolist(), mb.ct_id.tolist()))
+    d_slots = torch.from_numpy(mb.slots).to("cuda")
+    d_ct = torch.empty(mb.ct_words, dtype=torch.int64, device="cuda")
+    out = {"batch": int(len(mb.ct_id)), "ring_degrees": [ps.n for ps in W_MIXED.params],
+           "per_degree": [int((mb.ctx_idx == k).sum()) for k in range(len(W_MIXED.params))],
+           "ciphertext_gib": mb.ct_words * 8 / 2 ** 30}
+    for name, sch in (("zinc", 1), ("vanilla", 0)):
+        plan = zinc.Plan(ctxs, items, sch)
+        for _ in range(max(1, warmup)):
+            plan.launch(d_slots, d_ct)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(steps):
+            plan.launch(d_slots, d_ct)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / steps
+        out[f"{name}_ms"] = ms
+        out[f"{name}_enc_per_s"] = len(mb.ct_id) / (ms / 1e3)
+        plan.close()
+        print(f"[bench] mixed {name}: {ms:.3f} ms", file=sys.stderr, flush=True)
+    out["zinc_over_vanilla"] = out["vanilla_ms"] / out["zinc_ms"]
+    for c in ctxs:
+        c.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -120,6 +164,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--scheme", choices=["both", "zinc", "vanilla"], default="both")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-degree plan measurement")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="also run one torch copy of this many MiB (reference kernel for HBM byte counters)")
     args = ap.parse_args()
@@ -220,6 +265,8 @@ def main():
         line[f"{name}_kernel_ms"] = res[name]["kernel_ms"]
     if "vanilla" in res and "zinc" in res:
         line["zinc_over_vanilla"] = res["vanilla"]["ms_per_step"] / res["zinc"]["ms_per_step"]
+    if not args.no_mixed:
+        line["mixed_b2048"] = bench_mixed(args.steps, args.warmup)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(ws, sch, args.cpu_budget)
     print(json.dumps(line), flush=True)

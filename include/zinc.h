@@ -196,9 +196,12 @@ zinc_status zinc_device_errors(zinc_ctx* ctx, uint32_t* flags);
  * of its ciphertext ([2][L][N] of its context) in the ciphertext buffer, and its
  * ct_id.  zinc_plan_create copies the items to the device and sorts them by
  * cost; the plan keeps pointers to the contexts, which must outlive it.
- * zinc_plan_launch encrypts every item in one launch (the first launch on a
- * stream captures a HIP graph, later launches replay it when the buffers are
- * the same).  The buffers must stay valid until the launch completes. */
+ * zinc_plan_launch encrypts every item in one persistent launch on `stream`:
+ * the first call records the launch sequence as a HIP graph (on a private
+ * stream, so any caller stream works, the null stream included), later calls
+ * with the same buffers replay it, and new buffers are recorded again.  The
+ * buffers must stay valid until the launch completes; launches of one plan
+ * must not overlap (they share the plan's work counter). */
 typedef struct zinc_item {
     uint32_t ctx_idx;
     uint32_t reserved;

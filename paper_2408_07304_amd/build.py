@@ -11,7 +11,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libzinc.so")
-SOURCES = ["capi.cpp", "host_math.cpp", "kernels.hip", "kernels_split.hip"]
+SOURCES = ["capi.cpp", "host_math.cpp", "plan.cpp", "kernels.hip", "kernels_split.hip", "kernels_plan.hip"]
 ARCH = os.environ.get("ZINC_OFFLOAD_ARCH", "gfx950")
 
 # Packed-FP32 instructions are disabled for all device code.

@@ -22,6 +22,8 @@ static zinc_status fail(zinc_status code, const std::string& msg) {
     return code;
 }
 
+zinc_status plan_fail(zinc_status code, const std::string& msg) { return fail(code, msg); }
+
 static zinc_status hip_fail(hipError_t e, const char* what) {
     return fail(ZINC_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
@@ -407,16 +409,5 @@ zinc_status zinc_export_keys(zinc_ctx* c, uint64_t* sk, uint64_t* pk, uint64_t* 
         e = hipMemcpyAsync(zero, c->dev.zero, nb * 2 * c->L, hipMemcpyDeviceToDevice, s);
     return launched(e, "zinc_export_keys");
 }
-
-zinc_status zinc_plan_create(zinc_ctx* const*, uint32_t, const zinc_item*, uint32_t, int, zinc_plan** out) {
-    if (out) *out = nullptr;
-    return fail(ZINC_E_INVAL, "zinc_plan_create: mixed-shape plans are not available in this build");
-}
-
-zinc_status zinc_plan_launch(zinc_plan*, const double*, uint64_t*, void*) {
-    return fail(ZINC_E_INVAL, "zinc_plan_launch: mixed-shape plans are not available in this build");
-}
-
-zinc_status zinc_plan_destroy(zinc_plan*) { return ZINC_OK; }
 
 }  // extern "C"

@@ -10,131 +10,23 @@
 
 namespace zinc {
 
-// coefficients per thread (R) = 16 for every supported ring degree
-template <int LOGN>
-struct Cfg;
-template <>
-struct Cfg<12> { using G = Geom<12, 8>; };
-template <>
-struct Cfg<13> { using G = Geom<13, 9>; };
-template <>
-struct Cfg<14> { using G = Geom<14, 10>; };
-
 // ---------------------------------------------------------------------------
 // encryption
 // ---------------------------------------------------------------------------
-// One workgroup per ciphertext.  The encoded message (FROM_SLOTS) is stashed
-// as int64 in the ciphertext's own c1 slot of the last limb, in pass-0 layout;
-// each thread reads back only what it wrote, and the slot is overwritten only
-// by that limb's c1 epilogue, after the last read.  Vanilla keeps NTT(u) of the
-// current limb in that limb's c2 slot the same way until c2 is stored.
 template <int LOGN, int SCHEME, bool FROM_SLOTS>
 __global__ void __launch_bounds__(Cfg<LOGN>::G::T) __attribute__((amdgpu_waves_per_eu(4)))
 k_encrypt(DevParams p, EncArgs a) {
     using G = typename Cfg<LOGN>::G;
-    constexpr int R = G::R, N = G::N, T = G::T;
+    constexpr int N = G::N;
     __shared__ u64 lds[LdsWords<N>::value];
     __shared__ u64 tab[kCdtPad];
     const uint32_t t = threadIdx.x;
     const uint32_t b = blockIdx.x;
-    const u64 ct_id = a.ct_ids[b];
     load_cdt(tab, p.cdt, t);
     const uint32_t L = p.L;
-    u64* ct = a.ct + (size_t)b * 2 * L * N;
-    long long* stash = reinterpret_cast<long long*>(ct + (size_t)(L - 1) * N);
-    const u64* pt = a.pt + (size_t)b * L * N;
-
-    if constexpr (FROM_SLOTS) {
-        long long m[R];
-        encode_p0<G>(m, lds, p, a.slots + (size_t)b * a.n_slots, a.n_slots, t);
-        const uint32_t tp0 = G::tpart(0, t);
-#pragma unroll
-        for (int c = 0; c < R; ++c) stash[tp0 | G::cpart(0, c)] = m[c];
-    }
-
-    if constexpr (SCHEME == ZINC_SCHEME_ZINC) {
-        Packed8<R> e1, e2;
-        sample_gauss_p0<G>(e1, p, tab, ct_id, TAG_E1Z, t);
-        sample_gauss_p0<G>(e2, p, tab, ct_id, TAG_E2Z, t);
-#pragma unroll 1
-        for (uint32_t l = 0; l < L; ++l) {
-            const LimbConst lc = p.limbs[l];
-            const LimbNtt<G> nt{p, lc, l, lds, t};
-            const MessageIn<G, FROM_SLOTS> msg{stash, pt + (size_t)l * N, e1.fresh(), lc, G::tpart(0, opaque_tid(t))};
-            // c1 = zero1 + NTT(m + e1')
-            nt.run([&](int c) { return msg.ri(c); }, [&](int c) { return msg.rf(c); });
-            {
-                const uint32_t tt = opaque_tid(t);
-                const u64* z = p.zero + (size_t)l * N;
-                u64* out = ct + (size_t)l * N;
-#pragma unroll
-                for (int i = 0; i < R; ++i) {
-                    const uint32_t k = tt + T * i;
-                    out[k] = addmod(nt.canon(k), z[k], lc.q);
-                }
-            }
-            // c2 = zero2 + NTT(e2')
-            const Packed8<R> e2l = e2.fresh();
-            nt.run([&](int c) { return small_mod(e2l.get(c), lc.q); }, [&](int c) { return (double)e2l.get(c); });
-            {
-                const uint32_t tt = opaque_tid(t);
-                const u64* z = p.zero + (size_t)(L + l) * N;
-                u64* out = ct + (size_t)(L + l) * N;
-#pragma unroll
-                for (int i = 0; i < R; ++i) {
-                    const uint32_t k = tt + T * i;
-                    out[k] = addmod(nt.canon(k), z[k], lc.q);
-                }
-            }
-        }
-    } else {
-        Packed8<R> u, e1, e2;
-        sample_ternary_p0<G>(u, p, ct_id, TAG_U, t);
-        sample_gauss_p0<G>(e1, p, tab, ct_id, TAG_E1, t);
-        sample_gauss_p0<G>(e2, p, tab, ct_id, TAG_E2, t);
-        const uint32_t M = p.M;
-#pragma unroll 1
-        for (uint32_t l = 0; l < L; ++l) {
-            const LimbConst lc = p.limbs[l];
-            const LimbNtt<G> nt{p, lc, l, lds, t};
-            u64* c1 = ct + (size_t)l * N;
-            u64* c2 = ct + (size_t)(L + l) * N;
-            // u_hat -> the c2 slot of this limb (natural order)
-            const Packed8<R> ul = u.fresh();
-            nt.run([&](int c) { return small_mod(ul.get(c), lc.q); }, [&](int c) { return (double)ul.get(c); });
-            {
-                const uint32_t tt = opaque_tid(t);
-#pragma unroll
-                for (int i = 0; i < R; ++i) c2[tt + T * i] = nt.canon(tt + T * i);
-            }
-            // c1 = pk1 u_hat + NTT(m + e1)
-            const MessageIn<G, FROM_SLOTS> msg{stash, pt + (size_t)l * N, e1.fresh(), lc, G::tpart(0, opaque_tid(t))};
-            nt.run([&](int c) { return msg.ri(c); }, [&](int c) { return msg.rf(c); });
-            {
-                const uint32_t tt = opaque_tid(t);
-                const u64* pk = p.pk + (size_t)l * N;
-                const u64* pks = p.pk_sh + (size_t)l * N;
-#pragma unroll
-                for (int i = 0; i < R; ++i) {
-                    const uint32_t k = tt + T * i;
-                    c1[k] = addmod(nt.canon(k), nt.mul(c2[k], pk[k], pks[k]), lc.q);
-                }
-            }
-            // c2 = pk2 u_hat + NTT(e2)
-            const Packed8<R> e2l = e2.fresh();
-            nt.run([&](int c) { return small_mod(e2l.get(c), lc.q); }, [&](int c) { return (double)e2l.get(c); });
-            {
-                const uint32_t tt = opaque_tid(t);
-                const u64* pk = p.pk + (size_t)(M + l) * N;
-                const u64* pks = p.pk_sh + (size_t)(M + l) * N;
-#pragma unroll
-                for (int i = 0; i < R; ++i) {
-                    const uint32_t k = tt + T * i;
-                    c2[k] = addmod(nt.canon(k), nt.mul(c2[k], pk[k], pks[k]), lc.q);
-                }
-            }
-        }
-    }
+    encrypt_item<LOGN, SCHEME, FROM_SLOTS>(p, a.slots + (size_t)b * a.n_slots, a.n_slots,
+                                          a.pt + (size_t)b * L * N, a.ct_ids[b], a.ct + (size_t)b * 2 * L * N,
+                                          lds, tab, t);
 }
 
 // ---------------------------------------------------------------------------

@@ -5,6 +5,16 @@
 
 namespace zinc {
 
+// coefficients per thread (R) = 16 for every supported ring degree
+template <int LOGN>
+struct Cfg;
+template <>
+struct Cfg<12> { using G = Geom<12, 8>; };
+template <>
+struct Cfg<13> { using G = Geom<13, 9>; };
+template <>
+struct Cfg<14> { using G = Geom<14, 10>; };
+
 struct EncArgs {
     const double* slots;     // [batch][n_slots] (FROM_SLOTS)
     uint32_t n_slots;
@@ -91,5 +101,117 @@ struct MessageIn {
         else return u64_to_fp(pt[k]) + (double)e.get(c);
     }
 };
+
+// One workgroup per ciphertext.  The encoded message (FROM_SLOTS) is stashed
+// as int64 in the ciphertext's own c1 slot of the last limb, in pass-0 layout;
+// each thread reads back only what it wrote, and the slot is overwritten only
+// by that limb's c1 epilogue, after the last read.  Vanilla keeps NTT(u) of the
+// current limb in that limb's c2 slot the same way until c2 is stored.
+//
+// Encrypt one ciphertext with the threads t in [0, G::T) of a group whose
+// barriers every thread of the workgroup reaches (the whole workgroup, or one
+// of several equal groups running the same ring degree in lockstep).  lds is
+// the group's exchange buffer (LdsWords<N> words), tab the chi table in LDS.
+template <int LOGN, int SCHEME, bool FROM_SLOTS>
+__device__ __forceinline__ void encrypt_item(const DevParams& p, const double* slots, uint32_t n_slots,
+                                             const u64* pt, u64 ct_id, u64* ct, u64* lds, const u64* tab,
+                                             uint32_t t) {
+    using G = typename Cfg<LOGN>::G;
+    constexpr int R = G::R, N = G::N, T = G::T;
+    const uint32_t L = p.L;
+    long long* stash = reinterpret_cast<long long*>(ct + (size_t)(L - 1) * N);
+
+    if constexpr (FROM_SLOTS) {
+        long long m[R];
+        encode_p0<G>(m, lds, p, slots, n_slots, t);
+        const uint32_t tp0 = G::tpart(0, t);
+#pragma unroll
+        for (int c = 0; c < R; ++c) stash[tp0 | G::cpart(0, c)] = m[c];
+    }
+
+    if constexpr (SCHEME == ZINC_SCHEME_ZINC) {
+        Packed8<R> e1, e2;
+        sample_gauss_p0<G>(e1, p, tab, ct_id, TAG_E1Z, t);
+        sample_gauss_p0<G>(e2, p, tab, ct_id, TAG_E2Z, t);
+#pragma unroll 1
+        for (uint32_t l = 0; l < L; ++l) {
+            const LimbConst lc = p.limbs[l];
+            const LimbNtt<G> nt{p, lc, l, lds, t};
+            const MessageIn<G, FROM_SLOTS> msg{stash, pt + (size_t)l * N, e1.fresh(), lc, G::tpart(0, opaque_tid(t))};
+            // c1 = zero1 + NTT(m + e1')
+            nt.run([&](int c) { return msg.ri(c); }, [&](int c) { return msg.rf(c); });
+            {
+                const uint32_t tt = opaque_tid(t);
+                const u64* z = p.zero + (size_t)l * N;
+                u64* out = ct + (size_t)l * N;
+#pragma unroll
+                for (int i = 0; i < R; ++i) {
+                    const uint32_t k = tt + T * i;
+                    out[k] = addmod(nt.canon(k), z[k], lc.q);
+                }
+            }
+            // c2 = zero2 + NTT(e2')
+            const Packed8<R> e2l = e2.fresh();
+            nt.run([&](int c) { return small_mod(e2l.get(c), lc.q); }, [&](int c) { return (double)e2l.get(c); });
+            {
+                const uint32_t tt = opaque_tid(t);
+                const u64* z = p.zero + (size_t)(L + l) * N;
+                u64* out = ct + (size_t)(L + l) * N;
+#pragma unroll
+                for (int i = 0; i < R; ++i) {
+                    const uint32_t k = tt + T * i;
+                    out[k] = addmod(nt.canon(k), z[k], lc.q);
+                }
+            }
+        }
+    } else {
+        Packed8<R> u, e1, e2;
+        sample_ternary_p0<G>(u, p, ct_id, TAG_U, t);
+        sample_gauss_p0<G>(e1, p, tab, ct_id, TAG_E1, t);
+        sample_gauss_p0<G>(e2, p, tab, ct_id, TAG_E2, t);
+        const uint32_t M = p.M;
+#pragma unroll 1
+        for (uint32_t l = 0; l < L; ++l) {
+            const LimbConst lc = p.limbs[l];
+            const LimbNtt<G> nt{p, lc, l, lds, t};
+            u64* c1 = ct + (size_t)l * N;
+            u64* c2 = ct + (size_t)(L + l) * N;
+            // u_hat -> the c2 slot of this limb (natural order)
+            const Packed8<R> ul = u.fresh();
+            nt.run([&](int c) { return small_mod(ul.get(c), lc.q); }, [&](int c) { return (double)ul.get(c); });
+            {
+                const uint32_t tt = opaque_tid(t);
+#pragma unroll
+                for (int i = 0; i < R; ++i) c2[tt + T * i] = nt.canon(tt + T * i);
+            }
+            // c1 = pk1 u_hat + NTT(m + e1)
+            const MessageIn<G, FROM_SLOTS> msg{stash, pt + (size_t)l * N, e1.fresh(), lc, G::tpart(0, opaque_tid(t))};
+            nt.run([&](int c) { return msg.ri(c); }, [&](int c) { return msg.rf(c); });
+            {
+                const uint32_t tt = opaque_tid(t);
+                const u64* pk = p.pk + (size_t)l * N;
+                const u64* pks = p.pk_sh + (size_t)l * N;
+#pragma unroll
+                for (int i = 0; i < R; ++i) {
+                    const uint32_t k = tt + T * i;
+                    c1[k] = addmod(nt.canon(k), nt.mul(c2[k], pk[k], pks[k]), lc.q);
+                }
+            }
+            // c2 = pk2 u_hat + NTT(e2)
+            const Packed8<R> e2l = e2.fresh();
+            nt.run([&](int c) { return small_mod(e2l.get(c), lc.q); }, [&](int c) { return (double)e2l.get(c); });
+            {
+                const uint32_t tt = opaque_tid(t);
+                const u64* pk = p.pk + (size_t)(M + l) * N;
+                const u64* pks = p.pk_sh + (size_t)(M + l) * N;
+#pragma unroll
+                for (int i = 0; i < R; ++i) {
+                    const uint32_t k = tt + T * i;
+                    c2[k] = addmod(nt.canon(k), nt.mul(c2[k], pk[k], pks[k]), lc.q);
+                }
+            }
+        }
+    }
+}
 
 }  // namespace zinc

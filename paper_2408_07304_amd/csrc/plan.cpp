@@ -1,0 +1,175 @@
+// Mixed-shape plans: many ciphertexts of several contexts (ring degrees and
+// moduli chains) encrypted by one persistent launch, captured once as a HIP
+// graph and replayed.
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "zinc_internal.h"
+
+struct zinc_plan {
+    std::vector<zinc_ctx*> ctxs;
+    int scheme = 0;
+    void* d_block = nullptr;            // contexts, items, units, counter, dummy outputs
+    zinc::PlanDev dev{};
+    size_t n_items = 0;
+    // captured graph and what it was captured with
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t cap_stream = nullptr;   // private stream the graph is recorded on
+    const double* cap_slots = nullptr;
+    uint64_t* cap_ct = nullptr;
+};
+
+namespace zinc {
+zinc_status plan_fail(zinc_status code, const std::string& msg);
+}
+
+using namespace zinc;
+
+static uint32_t units_per_group(uint32_t log_n) { return log_n == 12 ? 4u : log_n == 13 ? 2u : 1u; }
+
+static void drop_graph(zinc_plan* p) {
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    p->exec = nullptr;
+    p->graph = nullptr;
+}
+
+extern "C" {
+
+zinc_status zinc_plan_create(zinc_ctx* const* ctxs, uint32_t n_ctx, const zinc_item* items, uint32_t n_items,
+                             int scheme, zinc_plan** out) {
+    if (!out) return plan_fail(ZINC_E_INVAL, "zinc_plan_create: null output");
+    *out = nullptr;
+    if (!ctxs || n_ctx == 0 || (!items && n_items)) return plan_fail(ZINC_E_INVAL, "zinc_plan_create: null argument");
+    if (scheme != ZINC_SCHEME_VANILLA && scheme != ZINC_SCHEME_ZINC)
+        return plan_fail(ZINC_E_INVAL, "zinc_plan_create: scheme must be 0 (vanilla) or 1 (zinc)");
+    for (uint32_t c = 0; c < n_ctx; ++c) {
+        if (!ctxs[c]) return plan_fail(ZINC_E_INVAL, "zinc_plan_create: null context");
+        if (!ctxs[c]->keyed) return plan_fail(ZINC_E_STATE, "zinc_plan_create: context without keys");
+        if (scheme == ZINC_SCHEME_ZINC && !ctxs[c]->precomputed)
+            return plan_fail(ZINC_E_STATE, "zinc_plan_create: context without a cached Enc(0)");
+    }
+    for (uint32_t i = 0; i < n_items; ++i) {
+        if (items[i].ctx_idx >= n_ctx) return plan_fail(ZINC_E_INVAL, "zinc_plan_create: item context out of range");
+        if (items[i].ct_id >= (1ull << 63)) return plan_fail(ZINC_E_INVAL, "zinc_plan_create: ct_id must be < 2^63");
+    }
+    // Group items by context; contexts in decreasing cost per ciphertext, so
+    // the largest units come first (longest-processing-time order).
+    std::vector<uint32_t> order(n_ctx);
+    for (uint32_t c = 0; c < n_ctx; ++c) order[c] = c;
+    auto cost = [&](uint32_t c) { return (double)ctxs[c]->L * ctxs[c]->n * ctxs[c]->log_n; };
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return cost(a) > cost(b); });
+    std::vector<PlanItem> dev_items;
+    std::vector<PlanUnit> units;
+    uint64_t dummy_words = 0;
+    std::vector<std::vector<uint32_t>> per_ctx(n_ctx);
+    for (uint32_t i = 0; i < n_items; ++i) per_ctx[items[i].ctx_idx].push_back(i);
+    for (uint32_t c : order) {
+        const zinc_ctx* cx = ctxs[c];
+        const uint32_t g = units_per_group(cx->log_n);
+        const uint64_t ct_words = 2ull * cx->L * cx->n;
+        const auto& lst = per_ctx[c];
+        for (size_t s = 0; s < lst.size(); s += g) {
+            PlanUnit u{c, cx->log_n, (uint32_t)dev_items.size(), g};
+            for (uint32_t k = 0; k < g; ++k) {
+                if (s + k < lst.size()) {
+                    const zinc_item& it = items[lst[s + k]];
+                    dev_items.push_back(PlanItem{c, 0u, it.slot_off, it.ct_off, it.ct_id});
+                } else {   // pad with a copy of the unit's first item writing into the dummy buffer
+                    const zinc_item& it = items[lst[s]];
+                    dev_items.push_back(PlanItem{c, 1u, it.slot_off, dummy_words, it.ct_id});
+                    dummy_words += ct_words;
+                }
+            }
+            units.push_back(u);
+        }
+    }
+    zinc_plan* p = new (std::nothrow) zinc_plan();
+    if (!p) return plan_fail(ZINC_E_NOMEM, "host allocation failed");
+    p->ctxs.assign(ctxs, ctxs + n_ctx);
+    p->scheme = scheme;
+    p->n_items = n_items;
+    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+    const size_t b_ctx = al(sizeof(DevParams) * n_ctx), b_items = al(sizeof(PlanItem) * std::max<size_t>(1, dev_items.size()));
+    const size_t b_units = al(sizeof(PlanUnit) * std::max<size_t>(1, units.size())), b_cnt = 256;
+    const size_t b_dummy = al(8 * std::max<uint64_t>(1, dummy_words));
+    char* base = nullptr;
+    if (hipMalloc(&base, b_ctx + b_items + b_units + b_cnt + b_dummy) != hipSuccess) {
+        delete p;
+        return plan_fail(ZINC_E_NOMEM, "zinc_plan_create: device allocation failed");
+    }
+    p->d_block = base;
+    std::vector<DevParams> dp(n_ctx);
+    for (uint32_t c = 0; c < n_ctx; ++c) dp[c] = ctxs[c]->dev;
+    hipError_t e = hipMemcpy(base, dp.data(), sizeof(DevParams) * n_ctx, hipMemcpyHostToDevice);
+    if (e == hipSuccess && !dev_items.empty())
+        e = hipMemcpy(base + b_ctx, dev_items.data(), sizeof(PlanItem) * dev_items.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !units.empty())
+        e = hipMemcpy(base + b_ctx + b_items, units.data(), sizeof(PlanUnit) * units.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(base);
+        delete p;
+        return plan_fail(ZINC_E_HIP, std::string("zinc_plan_create: upload failed: ") + hipGetErrorString(e));
+    }
+    int dev = 0, cus = 256;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    PlanDev& d = p->dev;
+    d.ctxs = reinterpret_cast<const DevParams*>(base);
+    d.items = reinterpret_cast<const PlanItem*>(base + b_ctx);
+    d.units = reinterpret_cast<const PlanUnit*>(base + b_ctx + b_items);
+    d.n_units = (uint32_t)units.size();
+    d.counter = reinterpret_cast<uint32_t*>(base + b_ctx + b_items + b_units);
+    d.dummy = reinterpret_cast<uint64_t*>(base + b_ctx + b_items + b_units + b_cnt);
+    d.grid = (uint32_t)std::max(1, std::min<int>(cus, (int)std::max<uint32_t>(1, d.n_units)));
+    *out = p;
+    return ZINC_OK;
+}
+
+zinc_status zinc_plan_launch(zinc_plan* p, const double* slots, uint64_t* ct, void* stream) {
+    if (!p) return plan_fail(ZINC_E_INVAL, "zinc_plan_launch: null plan");
+    if (p->n_items == 0) return ZINC_OK;
+    if (!slots || !ct) return plan_fail(ZINC_E_INVAL, "zinc_plan_launch: null buffer");
+    hipStream_t s = (hipStream_t)stream;
+    if (!p->exec || p->cap_slots != slots || p->cap_ct != ct) {
+        // Record the launch sequence on the plan's own stream (the caller's may
+        // be the null stream, which cannot be captured); nothing runs here.
+        drop_graph(p);
+        hipError_t e = hipSuccess;
+        if (!p->cap_stream) e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return plan_fail(ZINC_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+        hipError_t le = launch_plan(p->dev, p->scheme, slots, ct, p->cap_stream);
+        e = hipStreamEndCapture(p->cap_stream, &p->graph);
+        if (le != hipSuccess || e != hipSuccess) {
+            drop_graph(p);
+            return plan_fail(ZINC_E_HIP, std::string("graph capture: ") + hipGetErrorString(le != hipSuccess ? le : e));
+        }
+        e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            drop_graph(p);
+            return plan_fail(ZINC_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+        }
+        p->cap_slots = slots;
+        p->cap_ct = ct;
+    }
+    hipError_t e = hipGraphLaunch(p->exec, s);
+    if (e != hipSuccess) return plan_fail(ZINC_E_HIP, std::string("graph launch: ") + hipGetErrorString(e));
+    return ZINC_OK;
+}
+
+zinc_status zinc_plan_destroy(zinc_plan* p) {
+    if (!p) return ZINC_OK;
+    (void)hipDeviceSynchronize();
+    drop_graph(p);
+    if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+    if (p->d_block) (void)hipFree(p->d_block);
+    delete p;
+    return ZINC_OK;
+}
+
+}  // extern "C"

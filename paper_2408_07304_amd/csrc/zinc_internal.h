@@ -56,6 +56,34 @@ struct DevParams {
     uint32_t* err;                // sticky device error flags
 };
 
+// One ciphertext of a mixed-shape plan (device copy of a zinc_item).
+struct PlanItem {
+    uint32_t ctx;            // index into the plan's contexts
+    uint32_t dummy;          // 1: padding of a partial unit, output goes to the plan's dummy buffer
+    uint64_t slot_off;       // float64 offset of the slot vector (N/2 values)
+    uint64_t ct_off;         // uint64 offset of the ciphertext ([2][L][N])
+    uint64_t ct_id;
+};
+
+// A unit of work: `count` consecutive items of one context, all encrypted by
+// one workgroup (4, 2, 1, 1 items for ring degree 4096, 8192, 16384, 32768).
+struct PlanUnit {
+    uint32_t ctx;
+    uint32_t log_n;
+    uint32_t first;
+    uint32_t count;
+};
+
+struct PlanDev {
+    const DevParams* ctxs;
+    const PlanItem* items;
+    const PlanUnit* units;
+    uint32_t n_units;
+    uint32_t grid;           // persistent workgroups
+    uint32_t* counter;
+    uint64_t* dummy;
+};
+
 }  // namespace zinc
 
 struct zinc_ctx {
@@ -106,6 +134,9 @@ hipError_t launch_ntt(const DevParams& p, bool inverse, uint32_t limb, uint64_t*
                       uint32_t n_polys, hipStream_t s);
 hipError_t launch_sample(const DevParams& p, int kind, uint32_t tag, uint32_t limb,
                          const uint64_t* ct_ids, uint32_t batch, void* out, hipStream_t s);
+
+// mixed-shape plans (kernels_plan.hip)
+hipError_t launch_plan(const PlanDev& d, int scheme, const double* slots, uint64_t* ct, hipStream_t s);
 
 // ring degree 32768 (kernels_split.hip)
 hipError_t launch_split_keygen(const DevParams& p, uint64_t* sk, uint64_t* sk_sh, uint64_t* pk,

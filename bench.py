@@ -47,7 +47,8 @@ def peak_bfly_per_s(limbs: int, fp64_mask: int) -> float:
 
 
 HBM_PEAK_BYTES_PER_S = 8.0e12
-KERNEL_SOURCES = ("paper_2408_07304_amd/csrc/kernels.hip", "paper_2408_07304_amd/csrc/device.h")
+KERNEL_SOURCES = ("paper_2408_07304_amd/csrc/kernels.hip", "paper_2408_07304_amd/csrc/kernels_common.h",
+                  "paper_2408_07304_amd/csrc/device.h")
 
 
 def kernel_hash() -> str:
@@ -111,7 +112,21 @@ def cpu_baseline(ws, scheme: int, budget_s: float):
                       f"{'Zinc' if scheme == 1 else 'vanilla'} encrypt), {threads} threads, {dt:.1f} s"}
 
 
-def bench_mixed(steps: int, warmup: int) -> dict:
+def mixed_contexts():
+    """Keyed and precomputed contexts of the four mixed-workload parameter sets."""
+    import paper_2408_07304_amd as zinc
+    from paper_2408_07304_amd.workloads import W_MIXED
+
+    ctxs = []
+    for ps in W_MIXED.params:
+        c = zinc.context_for(ps)
+        c.keygen()
+        c.precompute()
+        ctxs.append(c)
+    return ctxs
+
+
+def bench_mixed(ctxs, steps: int, warmup: int) -> dict:
     """The mixed batch: 2048 plaintexts, ring degree drawn per plaintext from
     {4096, 8192, 16384, 32768}, encrypted by one persistent plan launch
     (captured as a HIP graph on the first launch, replayed after)."""
@@ -120,12 +135,6 @@ def bench_mixed(steps: int, warmup: int) -> dict:
     import paper_2408_07304_amd as zinc
     from paper_2408_07304_amd.workloads import W_MIXED, make_mixed
 
-    ctxs = []
-    for ps in W_MIXED.params:
-        c = zinc.context_for(ps)
-        c.keygen()
-        c.precompute()
-        ctxs.append(c)
     mb = make_mixed(W_MIXED)
     items = list(zip(mb.ctx_idx.tolist(), mb.slot_off.tolist(), mb.ct_off.tolist(), mb.ct_id.tolist()))
     d_slots = torch.from_numpy(mb.slots).to("cuda")
@@ -150,8 +159,48 @@ def bench_mixed(steps: int, warmup: int) -> dict:
         plan.close()
         print(f"[bench] mixed {name}: {ms:.3f} ms", file=sys.stderr, flush=True)
     out["zinc_over_vanilla"] = out["vanilla_ms"] / out["zinc_ms"]
-    for c in ctxs:
-        c.close()
+    del d_ct, d_slots
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_serving(ctxs, saturated_enc_per_s: float, n_requests: int, warm: int, n_streams: int,
+                  max_batch: int, budget_gib: float) -> dict:
+    """Open-loop serving: Poisson arrivals at 0.7 x the vanilla mixed-batch
+    throughput (in requests/s, requests of 1..64 plaintexts of one parameter
+    set each), the same trace replayed for both schemes; latency = completion
+    observed on the host - scheduled arrival, over the requests after the
+    first `warm`."""
+    import numpy as np
+    import torch
+
+    import paper_2408_07304_amd as zinc
+    from paper_2408_07304_amd.workloads import W_MIXED, make_trace, trace_requests
+
+    mean_pt = 32.5
+    rate = 0.7 * saturated_enc_per_s / mean_pt
+    tr = make_trace(n_requests + warm, rate, W_MIXED.params, seed=5, pool=256)
+    req = trace_requests(tr)
+    d_slots = torch.from_numpy(tr.slots).to("cuda")
+    torch.cuda.synchronize()
+    out = {"requests": n_requests, "warmup_requests": warm, "offered_req_per_s": rate,
+           "offered_enc_per_s": rate * mean_pt, "load_vs_vanilla_saturated": 0.7, "streams": n_streams,
+           "max_batch": max_batch, "hbm_budget_gib": budget_gib, "outputs": "server arena, discarded"}
+    for name, sch in (("zinc", 1), ("vanilla", 0)):
+        t0 = time.perf_counter()
+        times = zinc.serve_trace(ctxs, sch, req, tr.arrival_ns, d_slots, None, n_streams=n_streams,
+                                 max_batch=max_batch, hbm_budget=int(budget_gib * 2 ** 30))
+        wall = time.perf_counter() - t0
+        m = slice(warm, None)
+        lat = (times["done_ns"][m] - times["submit_ns"][m]).astype(np.float64) / 1e6
+        span = (times["done_ns"][m].max() - times["submit_ns"][m].min()) / 1e9
+        nb = len(np.unique(times["batch"]))
+        out[name] = {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                     "mean_ms": float(lat.mean()), "max_ms": float(lat.max()),
+                     "enc_per_s": float(tr.n_pt[m].sum() / span), "batches": nb,
+                     "mean_batch_plaintexts": float(tr.n_pt.sum() / nb), "replay_s": wall}
+        print(f"[bench] serving {name}: {out[name]}", file=sys.stderr, flush=True)
+    out["p99_vanilla_over_zinc"] = out["vanilla"]["p99_ms"] / out["zinc"]["p99_ms"]
     return out
 
 
@@ -164,7 +213,12 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--scheme", choices=["both", "zinc", "vanilla"], default="both")
-    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-degree plan measurement")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-degree plan and serving measurements")
+    ap.add_argument("--serve-requests", type=int, default=10000, help="measured requests of the serving replay")
+    ap.add_argument("--serve-warmup", type=int, default=500)
+    ap.add_argument("--serve-streams", type=int, default=4)
+    ap.add_argument("--serve-max-batch", type=int, default=512)
+    ap.add_argument("--serve-budget-gib", type=float, default=8.0)
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="also run one torch copy of this many MiB (reference kernel for HBM byte counters)")
     args = ap.parse_args()
@@ -266,7 +320,16 @@ def main():
     if "vanilla" in res and "zinc" in res:
         line["zinc_over_vanilla"] = res["vanilla"]["ms_per_step"] / res["zinc"]["ms_per_step"]
     if not args.no_mixed:
-        line["mixed_b2048"] = bench_mixed(args.steps, args.warmup)
+        del ct, z
+        torch.cuda.empty_cache()
+        mctx = mixed_contexts()
+        line["mixed_b2048"] = bench_mixed(mctx, args.steps, args.warmup)
+        if args.serve_requests > 0:
+            line["serving"] = bench_serving(mctx, line["mixed_b2048"]["vanilla_enc_per_s"], args.serve_requests,
+                                            args.serve_warmup, args.serve_streams, args.serve_max_batch,
+                                            args.serve_budget_gib)
+        for c in mctx:
+            c.close()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(ws, sch, args.cpu_budget)
     print(json.dumps(line), flush=True)

@@ -31,8 +31,8 @@
  *
  * Memory ownership: pointers named d_* are device memory owned by the caller
  * (contiguous, 8-byte aligned); the library never frees them and keeps no
- * pointer to them after a call returns, except inside a plan (see
- * zinc_plan_create).  The library owns its tables, keys and the Zinc cache.
+ * pointer to them after a call returns, except inside a plan or a server
+ * (see zinc_plan_create and zinc_server_create).  The library owns its tables, keys and the Zinc cache.
  *
  * Streams: `stream` is a hipStream_t (NULL = the null stream).  Calls enqueue
  * work and return; argument and state errors are reported synchronously.  A
@@ -79,6 +79,7 @@ const char* zinc_last_error(void);
 
 typedef struct zinc_ctx zinc_ctx;
 typedef struct zinc_plan zinc_plan;
+typedef struct zinc_server zinc_server;
 
 /* Parameter set (Polynomials and Distributions; System Implementation).
  *   log_n      ring degree N = 2^log_n, 12..15.
@@ -214,6 +215,88 @@ zinc_status zinc_plan_create(zinc_ctx* const* ctxs, uint32_t n_ctx, const zinc_i
                              uint32_t n_items, int scheme, zinc_plan** out);
 zinc_status zinc_plan_launch(zinc_plan* plan, const double* d_slots, uint64_t* d_ct, void* stream);
 zinc_status zinc_plan_destroy(zinc_plan* plan);
+
+/* ---- serving: admission, continuous batching, latency ---------------------
+ * A server holds resident contexts (keys, tables and, for Zinc, the cached
+ * Enc(0)) and encrypts requests of 1..max_batch plaintexts of one context as
+ * they are submitted.  Each call of zinc_server_progress makes one scheduling
+ * pass without blocking:
+ *   1. reap: batches whose completion event has fired complete their
+ *      requests and return their output bytes to the budget;
+ *   2. admit: waiting requests, in submission order, are admitted while their
+ *      ciphertext bytes (n_pt * 2 * L * N * 8) fit in the free part of the
+ *      HBM budget (first fit over an arena of hbm_budget bytes; the first
+ *      request that does not fit blocks the ones behind it);
+ *   3. launch: every idle stream (of n_streams) takes admitted requests from
+ *      the front, up to max_batch plaintexts, as one batch: a persistent
+ *      launch of the mixed-shape kernel over all their plaintexts, whatever
+ *      their contexts, followed by a completion event.
+ * Plaintext k of a request reads the N/2 slots at d_slots + slot_off + k*N/2,
+ * gets ct_id + k, and writes its ciphertext at ct_off + k*2*L*N of the output
+ * base: d_ct if the configuration gives one, otherwise the server's own arena
+ * (hbm_budget bytes allocated at creation; the request's ciphertexts are
+ * discarded when it completes, which suits load generation).  Outputs are
+ * bit-identical to separate launches with the same ct_ids.
+ * The server's streams are its own (non-blocking, default priority): inputs
+ * must be complete on the device before their requests are submitted.  Times
+ * are nanoseconds of the host's monotonic clock since zinc_server_create.
+ * A server is used from one thread at a time. */
+
+typedef struct zinc_server_config {
+    int scheme;               /* ZINC_SCHEME_VANILLA or ZINC_SCHEME_ZINC              */
+    uint32_t n_streams;       /* concurrent batches, 1..16                            */
+    uint32_t max_batch;       /* plaintexts per launch, 1..65536                      */
+    uint32_t reserved;
+    uint64_t hbm_budget;      /* bytes of ciphertext admitted at once; 0: half of the
+                                 device's free memory at creation                     */
+    const double* d_slots;    /* base of every request's slots                        */
+    uint64_t* d_ct;           /* base of every request's output, or NULL (arena)      */
+} zinc_server_config;
+
+typedef struct zinc_request {
+    uint32_t ctx_idx;         /* context (index into the server's contexts)           */
+    uint32_t n_pt;            /* plaintexts, 1..max_batch                             */
+    uint64_t slot_off;        /* float64 offset of plaintext 0's slots in d_slots     */
+    uint64_t ct_off;          /* uint64 offset of ciphertext 0 in d_ct (unused with
+                                 the arena)                                           */
+    uint64_t ct_id;           /* ct_id of plaintext 0; ct_id + n_pt <= 2^63           */
+} zinc_request;
+
+typedef struct zinc_request_times {
+    uint64_t submit_ns;       /* submission (for a trace replay: scheduled arrival)   */
+    uint64_t admit_ns;        /* its output bytes were granted                        */
+    uint64_t launch_ns;       /* its batch was enqueued                               */
+    uint64_t done_ns;         /* its batch's completion was observed                  */
+    uint32_t batch;           /* sequence number of its batch                         */
+    uint32_t stream;          /* stream index that ran the batch                      */
+} zinc_request_times;
+
+/* The server keeps pointers to the contexts, which must outlive it; every
+ * context needs keys, and for the Zinc scheme its cached Enc(0). */
+zinc_status zinc_server_create(zinc_ctx* const* ctxs, uint32_t n_ctx, const zinc_server_config* cfg,
+                               zinc_server** out);
+/* Queue a request (host only, no device work).  ZINC_E_RANGE if its output
+ * alone exceeds hbm_budget or n_pt exceeds max_batch.  *ticket numbers
+ * requests 0, 1, 2, ... in submission order. */
+zinc_status zinc_server_submit(zinc_server* srv, const zinc_request* req, uint64_t* ticket);
+/* One scheduling pass (reap, admit, launch); *n_done (may be NULL) gets the
+ * number of requests completed by this pass. */
+zinc_status zinc_server_progress(zinc_server* srv, uint32_t* n_done);
+/* *done = 1 and *times filled once the request has completed, else *done = 0. */
+zinc_status zinc_server_query(zinc_server* srv, uint64_t ticket, int* done, zinc_request_times* times);
+/* Progress until every submitted request has completed. */
+zinc_status zinc_server_drain(zinc_server* srv);
+/* Waits for the server's streams, then frees its resources. */
+zinc_status zinc_server_destroy(zinc_server* srv);
+
+/* Open-loop replay of an arrival trace: creates a server, submits request r
+ * when the clock reaches arrival_ns[r] (nanoseconds after the replay starts,
+ * non-decreasing), runs zinc_server_progress in between, drains, and writes
+ * per-request times (relative to the replay start, submit_ns = the scheduled
+ * arrival) to times[n_req]. */
+zinc_status zinc_serve_trace(zinc_ctx* const* ctxs, uint32_t n_ctx, const zinc_server_config* cfg,
+                             const zinc_request* reqs, const uint64_t* arrival_ns, uint32_t n_req,
+                             zinc_request_times* times);
 
 /* ---- kernel-level entry points (parity testing of single steps) ---------- */
 

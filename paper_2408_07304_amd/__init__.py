@@ -52,6 +52,27 @@ class zinc_item(ctypes.Structure):
                 ("ct_off", ctypes.c_uint64), ("ct_id", ctypes.c_uint64)]
 
 
+class zinc_server_config(ctypes.Structure):
+    _fields_ = [("scheme", ctypes.c_int), ("n_streams", ctypes.c_uint32), ("max_batch", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("hbm_budget", ctypes.c_uint64), ("d_slots", ctypes.c_void_p),
+                ("d_ct", ctypes.c_void_p)]
+
+
+class zinc_request(ctypes.Structure):
+    _fields_ = [("ctx_idx", ctypes.c_uint32), ("n_pt", ctypes.c_uint32), ("slot_off", ctypes.c_uint64),
+                ("ct_off", ctypes.c_uint64), ("ct_id", ctypes.c_uint64)]
+
+
+class zinc_request_times(ctypes.Structure):
+    _fields_ = [("submit_ns", ctypes.c_uint64), ("admit_ns", ctypes.c_uint64), ("launch_ns", ctypes.c_uint64),
+                ("done_ns", ctypes.c_uint64), ("batch", ctypes.c_uint32), ("stream", ctypes.c_uint32)]
+
+
+# numpy layouts of zinc_request and zinc_request_times (arrays of requests)
+REQUEST_FIELDS = [("ctx_idx", "<u4"), ("n_pt", "<u4"), ("slot_off", "<u8"), ("ct_off", "<u8"), ("ct_id", "<u8")]
+TIMES_FIELDS = [("submit_ns", "<u8"), ("admit_ns", "<u8"), ("launch_ns", "<u8"), ("done_ns", "<u8"),
+                ("batch", "<u4"), ("stream", "<u4")]
+
 _lib = None
 _vp = ctypes.c_void_p
 _u32 = ctypes.c_uint32
@@ -74,6 +95,16 @@ _SIGS = {
                                         ctypes.c_int, ctypes.POINTER(_vp)]),
     "zinc_plan_launch": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "zinc_plan_destroy": (ctypes.c_int, [_vp]),
+    "zinc_server_create": (ctypes.c_int, [ctypes.POINTER(_vp), _u32, ctypes.POINTER(zinc_server_config),
+                                          ctypes.POINTER(_vp)]),
+    "zinc_server_submit": (ctypes.c_int, [_vp, ctypes.POINTER(zinc_request), ctypes.POINTER(ctypes.c_uint64)]),
+    "zinc_server_progress": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_uint32)]),
+    "zinc_server_query": (ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int),
+                                         ctypes.POINTER(zinc_request_times)]),
+    "zinc_server_drain": (ctypes.c_int, [_vp]),
+    "zinc_server_destroy": (ctypes.c_int, [_vp]),
+    "zinc_serve_trace": (ctypes.c_int, [ctypes.POINTER(_vp), _u32, ctypes.POINTER(zinc_server_config), _vp, _vp,
+                                        _u32, _vp]),
     "zinc_ntt_forward": (ctypes.c_int, [_vp, _u32, _vp, _u32, _vp]),
     "zinc_ntt_inverse": (ctypes.c_int, [_vp, _u32, _vp, _u32, _vp]),
     "zinc_sample": (ctypes.c_int, [_vp, ctypes.c_int, _u32, _u32, _vp, _u32, _vp, _vp]),
@@ -275,6 +306,80 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def _server_config(scheme, n_streams, max_batch, hbm_budget, slots, ct):
+    return zinc_server_config(int(scheme), int(n_streams), int(max_batch), 0, int(hbm_budget), _ptr(slots),
+                              _ptr(ct) if ct is not None else None)
+
+
+class Server:
+    """Admission and continuous batching over resident contexts (zinc_server_*).
+    `slots` is the base of every request's slot vectors; `ct` the base of their
+    outputs, or None for the server's own arena (outputs discarded)."""
+
+    def __init__(self, ctxs, scheme: int, slots, ct=None, n_streams: int = 4, max_batch: int = 512,
+                 hbm_budget: int = 8 << 30):
+        lib = load_library()
+        arr = (_vp * len(ctxs))(*[c.handle for c in ctxs])
+        cfg = _server_config(scheme, n_streams, max_batch, hbm_budget, slots, ct)
+        h = _vp()
+        _check(lib.zinc_server_create(arr, len(ctxs), ctypes.byref(cfg), ctypes.byref(h)))
+        self.handle = h.value
+        self._keep = (list(ctxs), slots, ct)
+
+    def submit(self, ctx_idx: int, n_pt: int, slot_off: int, ct_id: int, ct_off: int = 0) -> int:
+        r = zinc_request(int(ctx_idx), int(n_pt), int(slot_off), int(ct_off), int(ct_id))
+        t = ctypes.c_uint64()
+        _check(load_library().zinc_server_submit(self.handle, ctypes.byref(r), ctypes.byref(t)))
+        return t.value
+
+    def progress(self) -> int:
+        n = ctypes.c_uint32()
+        _check(load_library().zinc_server_progress(self.handle, ctypes.byref(n)))
+        return n.value
+
+    def query(self, ticket: int):
+        """None while the request runs, else its times as a dict."""
+        done = ctypes.c_int()
+        t = zinc_request_times()
+        _check(load_library().zinc_server_query(self.handle, int(ticket), ctypes.byref(done), ctypes.byref(t)))
+        if not done.value:
+            return None
+        return {name: getattr(t, name) for name, _ in zinc_request_times._fields_}
+
+    def drain(self):
+        _check(load_library().zinc_server_drain(self.handle))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load_library().zinc_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def serve_trace(ctxs, scheme: int, requests, arrival_ns, slots, ct=None, n_streams: int = 4,
+                max_batch: int = 512, hbm_budget: int = 8 << 30):
+    """Open-loop replay (zinc_serve_trace).  `requests` is a numpy array with
+    the fields of REQUEST_FIELDS, `arrival_ns` uint64 nanoseconds after the
+    start; returns a numpy array with the fields of TIMES_FIELDS."""
+    import numpy as np
+    req = np.ascontiguousarray(requests, dtype=np.dtype(REQUEST_FIELDS))
+    arr_ns = np.ascontiguousarray(arrival_ns, dtype=np.uint64)
+    if req.shape != arr_ns.shape or req.ndim != 1:
+        raise ValueError("requests and arrival_ns must be 1-D of equal length")
+    times = np.zeros(len(req), dtype=np.dtype(TIMES_FIELDS))
+    lib = load_library()
+    arr = (_vp * len(ctxs))(*[c.handle for c in ctxs])
+    cfg = _server_config(scheme, n_streams, max_batch, hbm_budget, slots, ct)
+    _check(lib.zinc_serve_trace(arr, len(ctxs), ctypes.byref(cfg), req.ctypes.data, arr_ns.ctypes.data,
+                                len(req), times.ctypes.data))
+    return times
 
 
 def context_for(ps) -> Context:

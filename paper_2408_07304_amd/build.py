@@ -11,7 +11,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libzinc.so")
-SOURCES = ["capi.cpp", "host_math.cpp", "plan.cpp", "kernels.hip", "kernels_split.hip", "kernels_plan.hip"]
+SOURCES = ["capi.cpp", "host_math.cpp", "plan.cpp", "server.cpp", "kernels.hip", "kernels_split.hip", "kernels_plan.hip"]
 ARCH = os.environ.get("ZINC_OFFLOAD_ARCH", "gfx950")
 
 # Packed-FP32 instructions are disabled for all device code.
@@ -39,10 +39,25 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
+def _stale(src: str) -> bool:
+    """True if src's object is missing or older than src or any header."""
+    obj = os.path.join(BUILD, src + ".o")
+    if not os.path.exists(obj):
+        return True
+    deps = [os.path.join(CSRC, src)] + [os.path.join(CSRC, h) for h in os.listdir(CSRC) if h.endswith(".h")]
+    deps.append(os.path.join(ROOT, "include", "zinc.h"))
+    t = os.path.getmtime(obj)
+    return any(os.path.getmtime(d) > t for d in deps)
+
+
+def build(verbose: bool = False, only_stale: bool = False) -> str:
+    """Compile every source (only_stale: only those whose object is out of
+    date, a development shortcut) and link libzinc.so."""
     os.makedirs(BUILD, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+    todo = [s for s in SOURCES if not only_stale or _stale(s)]
+    with ThreadPoolExecutor(max_workers=max(1, len(todo))) as ex:
+        list(ex.map(_compile, todo))
+    objs = [os.path.join(BUILD, s + ".o") for s in SOURCES]
     tmp = LIB + ".tmp"
     cmd = [_hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -55,4 +70,4 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, only_stale="--stale" in sys.argv[1:])

@@ -23,13 +23,62 @@ struct zinc_plan {
     uint64_t* cap_ct = nullptr;
 };
 
-namespace zinc {
-zinc_status plan_fail(zinc_status code, const std::string& msg);
-}
-
 using namespace zinc;
 
-static uint32_t units_per_group(uint32_t log_n) { return log_n == 12 ? 4u : log_n == 13 ? 2u : 1u; }
+namespace zinc {
+
+uint32_t plan_units_per_group(uint32_t log_n) { return log_n == 12 ? 4u : log_n == 13 ? 2u : 1u; }
+
+uint64_t plan_dummy_words(zinc_ctx* const* ctxs, uint32_t n_ctx) {
+    uint64_t w = 0;
+    for (uint32_t c = 0; c < n_ctx; ++c)
+        w += (plan_units_per_group(ctxs[c]->log_n) - 1) * 2ull * ctxs[c]->L * ctxs[c]->n;
+    return w;
+}
+
+int device_cu_count() {
+    int dev = 0, cus = 256;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    return cus > 0 ? cus : 256;
+}
+
+uint64_t build_plan_tables(zinc_ctx* const* ctxs, uint32_t n_ctx, const zinc_item* items, uint32_t n_items,
+                           std::vector<PlanItem>& dev_items, std::vector<PlanUnit>& units) {
+    // Contexts in decreasing cost per ciphertext, so the largest units come
+    // first (longest-processing-time order).
+    std::vector<uint32_t> order(n_ctx);
+    for (uint32_t c = 0; c < n_ctx; ++c) order[c] = c;
+    auto cost = [&](uint32_t c) { return (double)ctxs[c]->L * ctxs[c]->n * ctxs[c]->log_n; };
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return cost(a) > cost(b); });
+    dev_items.clear();
+    units.clear();
+    uint64_t dummy_words = 0;
+    std::vector<std::vector<uint32_t>> per_ctx(n_ctx);
+    for (uint32_t i = 0; i < n_items; ++i) per_ctx[items[i].ctx_idx].push_back(i);
+    for (uint32_t c : order) {
+        const zinc_ctx* cx = ctxs[c];
+        const uint32_t g = plan_units_per_group(cx->log_n);
+        const uint64_t ct_words = 2ull * cx->L * cx->n;
+        const auto& lst = per_ctx[c];
+        for (size_t s = 0; s < lst.size(); s += g) {
+            units.push_back(PlanUnit{c, cx->log_n, (uint32_t)dev_items.size(), g});
+            for (uint32_t k = 0; k < g; ++k) {
+                if (s + k < lst.size()) {
+                    const zinc_item& it = items[lst[s + k]];
+                    dev_items.push_back(PlanItem{c, 0u, it.slot_off, it.ct_off, it.ct_id});
+                } else {   // pad with a copy of the unit's first item writing into the dummy buffer
+                    const zinc_item& it = items[lst[s]];
+                    dev_items.push_back(PlanItem{c, 1u, it.slot_off, dummy_words, it.ct_id});
+                    dummy_words += ct_words;
+                }
+            }
+        }
+    }
+    return dummy_words;
+}
+
+}  // namespace zinc
 
 static void drop_graph(zinc_plan* p) {
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
@@ -57,37 +106,9 @@ zinc_status zinc_plan_create(zinc_ctx* const* ctxs, uint32_t n_ctx, const zinc_i
         if (items[i].ctx_idx >= n_ctx) return plan_fail(ZINC_E_INVAL, "zinc_plan_create: item context out of range");
         if (items[i].ct_id >= (1ull << 63)) return plan_fail(ZINC_E_INVAL, "zinc_plan_create: ct_id must be < 2^63");
     }
-    // Group items by context; contexts in decreasing cost per ciphertext, so
-    // the largest units come first (longest-processing-time order).
-    std::vector<uint32_t> order(n_ctx);
-    for (uint32_t c = 0; c < n_ctx; ++c) order[c] = c;
-    auto cost = [&](uint32_t c) { return (double)ctxs[c]->L * ctxs[c]->n * ctxs[c]->log_n; };
-    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return cost(a) > cost(b); });
     std::vector<PlanItem> dev_items;
     std::vector<PlanUnit> units;
-    uint64_t dummy_words = 0;
-    std::vector<std::vector<uint32_t>> per_ctx(n_ctx);
-    for (uint32_t i = 0; i < n_items; ++i) per_ctx[items[i].ctx_idx].push_back(i);
-    for (uint32_t c : order) {
-        const zinc_ctx* cx = ctxs[c];
-        const uint32_t g = units_per_group(cx->log_n);
-        const uint64_t ct_words = 2ull * cx->L * cx->n;
-        const auto& lst = per_ctx[c];
-        for (size_t s = 0; s < lst.size(); s += g) {
-            PlanUnit u{c, cx->log_n, (uint32_t)dev_items.size(), g};
-            for (uint32_t k = 0; k < g; ++k) {
-                if (s + k < lst.size()) {
-                    const zinc_item& it = items[lst[s + k]];
-                    dev_items.push_back(PlanItem{c, 0u, it.slot_off, it.ct_off, it.ct_id});
-                } else {   // pad with a copy of the unit's first item writing into the dummy buffer
-                    const zinc_item& it = items[lst[s]];
-                    dev_items.push_back(PlanItem{c, 1u, it.slot_off, dummy_words, it.ct_id});
-                    dummy_words += ct_words;
-                }
-            }
-            units.push_back(u);
-        }
-    }
+    const uint64_t dummy_words = build_plan_tables(ctxs, n_ctx, items, n_items, dev_items, units);
     zinc_plan* p = new (std::nothrow) zinc_plan();
     if (!p) return plan_fail(ZINC_E_NOMEM, "host allocation failed");
     p->ctxs.assign(ctxs, ctxs + n_ctx);
@@ -115,9 +136,7 @@ zinc_status zinc_plan_create(zinc_ctx* const* ctxs, uint32_t n_ctx, const zinc_i
         delete p;
         return plan_fail(ZINC_E_HIP, std::string("zinc_plan_create: upload failed: ") + hipGetErrorString(e));
     }
-    int dev = 0, cus = 256;
-    (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const int cus = device_cu_count();
     PlanDev& d = p->dev;
     d.ctxs = reinterpret_cast<const DevParams*>(base);
     d.items = reinterpret_cast<const PlanItem*>(base + b_ctx);

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string>
+#include <vector>
 
 #include "../../include/zinc.h"
 
@@ -137,6 +138,18 @@ hipError_t launch_sample(const DevParams& p, int kind, uint32_t tag, uint32_t li
 
 // mixed-shape plans (kernels_plan.hip)
 hipError_t launch_plan(const PlanDev& d, int scheme, const double* slots, uint64_t* ct, hipStream_t s);
+
+// plan tables (plan.cpp), shared by plans and the server
+uint32_t plan_units_per_group(uint32_t log_n);
+// Group items by context, contexts in decreasing cost per ciphertext, and cut
+// each group into units of plan_units_per_group items; a partial unit is
+// padded with copies of its first item whose outputs go to a dummy buffer.
+// Returns the dummy buffer's size in words (at most plan_dummy_words).
+uint64_t build_plan_tables(zinc_ctx* const* ctxs, uint32_t n_ctx, const zinc_item* items, uint32_t n_items,
+                           std::vector<PlanItem>& dev_items, std::vector<PlanUnit>& units);
+uint64_t plan_dummy_words(zinc_ctx* const* ctxs, uint32_t n_ctx);
+int device_cu_count();
+zinc_status plan_fail(zinc_status code, const std::string& msg);
 
 // ring degree 32768 (kernels_split.hip)
 hipError_t launch_split_keygen(const DevParams& p, uint64_t* sk, uint64_t* sk_sh, uint64_t* pk,

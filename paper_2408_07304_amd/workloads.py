@@ -12,7 +12,7 @@ clipped standard normal, the distributions of the benchmark configurations.
 """
 from __future__ import annotations
 
-from dataclasses import dataclass, field
+from dataclasses import dataclass
 
 import numpy as np
 
@@ -125,26 +125,71 @@ def make_mixed(w: Workload = W_MIXED, count: int | None = None) -> MixedBatch:
 
 
 @dataclass
-class Request:
-    arrival: float         # seconds from trace start
-    param: int             # index into the parameter-set tuple
-    count: int             # plaintexts in the request
-    rid: int
-    slots: np.ndarray = field(repr=False, default=None)
+class Trace:
+    """Open-loop arrival trace of a serving workload.  Per request: arrival
+    (ns after the start), parameter-set index, plaintext count, offset of its
+    first slot vector in `slots` (float64 elements; plaintext k follows at
+    + k*N/2), first ct_id (plaintext k gets ct_id + k; identifiers are
+    consecutive over the trace) and offset of its first ciphertext in a buffer
+    of ct_words uint64 holding every output in request order."""
+    params: tuple
+    arrival_ns: np.ndarray
+    ctx_idx: np.ndarray
+    n_pt: np.ndarray
+    slot_off: np.ndarray
+    ct_id: np.ndarray
+    ct_off: np.ndarray
+    ct_words: int
+    slots: np.ndarray          # flat float64 slot pool
+
+    def __len__(self) -> int:
+        return len(self.n_pt)
+
+    @property
+    def plaintexts(self) -> int:
+        return int(self.n_pt.sum())
 
 
-def make_trace(n_requests: int, rate_per_s: float, params: tuple = W_MIXED.params,
-               seed: int = 5, max_count: int = 64, with_slots: bool = True) -> list:
-    """Open-loop Poisson arrival trace: exponential inter-arrival times at
-    rate_per_s, request size uniform on {1..max_count}, parameter set uniform
-    over `params`, slots uniform on [-1, 1)."""
+def make_trace(n_requests: int, rate_per_s: float, params: tuple = W_MIXED.params, seed: int = 5,
+               max_count: int = 64, pool: int | None = None) -> Trace:
+    """Poisson arrivals at rate_per_s (exponential gaps), request size uniform
+    on {1..max_count}, parameter set uniform over `params`, slots uniform on
+    [-1, 1).  pool=None gives every plaintext its own slot vector; otherwise
+    each parameter set has a pool of `pool` (>= max_count) slot vectors and a
+    request reads `count` consecutive ones from a uniformly drawn start."""
     rng = np.random.default_rng(seed)
-    t = 0.0
-    out = []
-    for r in range(n_requests):
-        t += rng.exponential(1.0 / rate_per_s)
-        pi = int(rng.integers(0, len(params)))
-        cnt = int(rng.integers(1, max_count + 1))
-        s = slot_values(rng, cnt, params[pi].slots, "uniform") if with_slots else None
-        out.append(Request(t, pi, cnt, r, s))
+    gaps = rng.exponential(1.0 / rate_per_s, size=n_requests)
+    arrival_ns = np.round(np.cumsum(gaps) * 1e9).astype(np.uint64)
+    pidx = rng.integers(0, len(params), size=n_requests).astype(np.uint32)
+    cnt = rng.integers(1, max_count + 1, size=n_requests).astype(np.uint32)
+    ct_id = np.zeros(n_requests, dtype=np.uint64)
+    ct_id[1:] = np.cumsum(cnt[:-1], dtype=np.uint64)
+    words = np.array([2 * p.limbs * p.n for p in params], dtype=np.uint64)
+    per_req = cnt.astype(np.uint64) * words[pidx]
+    ct_off = np.zeros(n_requests, dtype=np.uint64)
+    ct_off[1:] = np.cumsum(per_req[:-1], dtype=np.uint64)
+    slot_off = np.zeros(n_requests, dtype=np.uint64)
+    if pool is None:
+        sizes = cnt.astype(np.uint64) * np.array([p.slots for p in params], dtype=np.uint64)[pidx]
+        slot_off[1:] = np.cumsum(sizes[:-1], dtype=np.uint64)
+        slots = rng.uniform(-1.0, 1.0, size=int(sizes.sum()))
+    else:
+        if pool < max_count:
+            raise ValueError("pool must hold at least max_count slot vectors")
+        base = np.cumsum([0] + [pool * p.slots for p in params])
+        slots = rng.uniform(-1.0, 1.0, size=int(base[-1]))
+        start = rng.integers(0, pool - cnt + 1)
+        per = np.array([p.slots for p in params], dtype=np.uint64)[pidx]
+        slot_off = np.asarray(base[:-1], dtype=np.uint64)[pidx] + start.astype(np.uint64) * per
+    return Trace(params, arrival_ns, pidx, cnt, slot_off, ct_id, ct_off, int(per_req.sum()), slots)
+
+
+def trace_requests(tr: Trace) -> np.ndarray:
+    """Requests of a trace as a structured array (ctx_idx, n_pt, slot_off,
+    ct_off, ct_id), the field layout of the library's request records."""
+    dt = np.dtype([("ctx_idx", "<u4"), ("n_pt", "<u4"), ("slot_off", "<u8"), ("ct_off", "<u8"),
+                   ("ct_id", "<u8")])
+    out = np.zeros(len(tr), dtype=dt)
+    out["ctx_idx"], out["n_pt"], out["slot_off"] = tr.ctx_idx, tr.n_pt, tr.slot_off
+    out["ct_off"], out["ct_id"] = tr.ct_off, tr.ct_id
     return out

@@ -48,6 +48,7 @@ def peak_bfly_per_s(limbs: int, fp64_mask: int) -> float:
 
 HBM_PEAK_BYTES_PER_S = 8.0e12
 KERNEL_SOURCES = ("paper_2408_07304_amd/csrc/kernels.hip", "paper_2408_07304_amd/csrc/kernels_common.h",
+                  "paper_2408_07304_amd/csrc/kernels_tiles.h",
                   "paper_2408_07304_amd/csrc/device.h")
 
 
@@ -213,6 +214,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--scheme", choices=["both", "zinc", "vanilla"], default="both")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default kernel configuration")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-degree plan and serving measurements")
     ap.add_argument("--serve-requests", type=int, default=10000, help="measured requests of the serving replay")
     ap.add_argument("--serve-warmup", type=int, default=500)
@@ -244,6 +246,10 @@ def main():
     ctx = zinc.context_for(ps)
     ctx.keygen()
     ctx.precompute()
+    tune = None
+    if not args.no_tune:
+        tune = ctx.autotune(batch=ws.batch)        # thread geometry and NTT arithmetic, outside the timed region
+        print(f"[bench] autotune: {tune}", file=sys.stderr, flush=True)
     z = torch.from_numpy(make_slots(ws)).to(dev)
     ids = torch.arange(ws.batch, dtype=torch.int64, device=dev)
     ct = torch.empty((ws.batch, 2, ps.limbs, ps.n), dtype=torch.int64, device=dev)
@@ -303,12 +309,14 @@ def main():
         "data": "synthetic",
         "config": {"workload": ws.name, "N": ps.n, "moduli_bits": list(ps.bits), "data_limbs": ps.limbs,
                    "scale_log2": int(math.log2(ps.scale)), "batch": ws.batch, "slots": ps.slots,
-                   "slot_values": ws.dist, "scheme": main_name, "fused_encode": True},
+                   "slot_values": ws.dist, "scheme": main_name, "fused_encode": True,
+                   "tuning": ctx.get_tuning(), "autotuned": tune is not None},
         "roofline": {"bound": "alu", "achieved": achieved / 1e9, "peak": peak / 1e9,
                      "unit": "Gbutterfly/s", "frac": achieved / peak,
                      "ntt_fp64_limbs": [l for l in range(ps.limbs) if (ctx.info()["ntt_fp64_mask"] >> l) & 1],
                      "traffic": traffic_from_profile(ws.name, main_name),
-                     "kernel": "k_encrypt (fused encode + sample + NTT + add)",
+                     "kernel": ("k_encrypt" if ctx.get_tuning()["tile"][sch] == 16 else "k_encrypt_tile")
+                     + " (fused encode + sample + NTT + add)",
                      "kernel_ms": r["kernel_ms"], "butterflies_per_launch": bfly,
                      "hbm_algorithmic_bytes_per_launch": ws.batch * algorithmic_bytes(ps.n, ps.limbs, ps.slots),
                      "hbm_frac": ws.batch * algorithmic_bytes(ps.n, ps.limbs, ps.slots)

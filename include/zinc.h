@@ -119,6 +119,8 @@ typedef struct zinc_info {
     uint32_t ntt_fp64_mask;     /* bit l set: limb l's forward NTT runs in exact
                                    FP64 arithmetic (moduli below 2^50), else in
                                    64-bit integer (Shoup) arithmetic          */
+    uint32_t tile[2];           /* coefficients per thread of the fused kernel
+                                   for vanilla [0] and Zinc [1] (see zinc_tuning) */
 } zinc_info;
 
 /* Create a context on the current HIP device: validate the parameters, derive
@@ -297,6 +299,48 @@ zinc_status zinc_server_destroy(zinc_server* srv);
 zinc_status zinc_serve_trace(zinc_ctx* const* ctxs, uint32_t n_ctx, const zinc_server_config* cfg,
                              const zinc_request* reqs, const uint64_t* arrival_ns, uint32_t n_req,
                              zinc_request_times* times);
+
+/* ---- tuning ----------------------------------------------------------------
+ * Two per-context choices change speed, never results: every combination
+ * gives bit-identical ciphertexts.
+ *   tile[s]        coefficients per thread of the fused encode + encrypt kernel
+ *                  that zinc_encrypt_slots runs for scheme s (0 vanilla,
+ *                  1 Zinc): 16 (default, every N), 8 (N = 4096 and 8192) or 32
+ *                  (N <= 16384).  N = 32768 has the single value 16.
+ *   ntt_fp64_mask  limbs whose forward NTT runs in exact FP64 arithmetic
+ *                  instead of 64-bit integer arithmetic; only limbs with a
+ *                  modulus below 2^50 may be set (default: all of those).
+ * Both need exclusive use of the context (no kernel of it in flight); the
+ * arithmetic choice also applies to plans and servers using the context. */
+typedef struct zinc_tuning {
+    uint32_t tile[2];
+    uint32_t ntt_fp64_mask;
+    uint32_t reserved;
+} zinc_tuning;
+
+typedef struct zinc_tune_result {
+    zinc_tuning chosen;
+    uint32_t from_cache;        /* 1: applied from the cache file, nothing timed */
+    uint32_t n_timed;           /* configurations timed                        */
+    double best_ms[2];          /* one batch, chosen configuration, per scheme  */
+    double default_ms[2];       /* one batch, default configuration (0: scheme
+                                   not timed)                                  */
+} zinc_tune_result;
+
+/* ZINC_E_INVAL for a tile the ring degree does not have or a mask bit on a
+ * limb whose modulus is 2^50 or more. */
+zinc_status zinc_set_tuning(zinc_ctx* ctx, const zinc_tuning* t);
+zinc_status zinc_get_tuning(const zinc_ctx* ctx, zinc_tuning* t);
+/* Time every combination of tiles and arithmetic on `batch` (1..65536)
+ * plaintexts of N/2 slots uniform on [-1, 1) (a fixed pseudo-random sequence)
+ * with zinc_encrypt_slots (vanilla, and Zinc when
+ * precomputed), on a private stream with HIP events (median of 5 runs after
+ * 2 warm-up runs), and keep the fastest.  cache_path (may be NULL) names a
+ * text file of earlier results keyed by device architecture, CU count, ring
+ * degree, moduli and batch: a matching entry is applied without timing, and a
+ * new result is added to the file.  Synchronous; needs keys
+ * (ZINC_E_STATE before zinc_keygen). */
+zinc_status zinc_autotune(zinc_ctx* ctx, uint32_t batch, const char* cache_path, zinc_tune_result* out);
 
 /* ---- kernel-level entry points (parity testing of single steps) ---------- */
 

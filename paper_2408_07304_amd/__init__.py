@@ -44,7 +44,17 @@ class zinc_info(ctypes.Structure):
                 ("psi", ctypes.c_uint64 * ZINC_MAX_MODULI), ("scale", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("cdt", ctypes.c_uint64 * 38),
                 ("plaintext_bytes", ctypes.c_size_t), ("ciphertext_bytes", ctypes.c_size_t),
-                ("keyed", ctypes.c_int), ("precomputed", ctypes.c_int), ("ntt_fp64_mask", ctypes.c_uint32)]
+                ("keyed", ctypes.c_int), ("precomputed", ctypes.c_int), ("ntt_fp64_mask", ctypes.c_uint32),
+                ("tile", ctypes.c_uint32 * 2)]
+
+
+class zinc_tuning(ctypes.Structure):
+    _fields_ = [("tile", ctypes.c_uint32 * 2), ("ntt_fp64_mask", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class zinc_tune_result(ctypes.Structure):
+    _fields_ = [("chosen", zinc_tuning), ("from_cache", ctypes.c_uint32), ("n_timed", ctypes.c_uint32),
+                ("best_ms", ctypes.c_double * 2), ("default_ms", ctypes.c_double * 2)]
 
 
 class zinc_item(ctypes.Structure):
@@ -105,6 +115,9 @@ _SIGS = {
     "zinc_server_destroy": (ctypes.c_int, [_vp]),
     "zinc_serve_trace": (ctypes.c_int, [ctypes.POINTER(_vp), _u32, ctypes.POINTER(zinc_server_config), _vp, _vp,
                                         _u32, _vp]),
+    "zinc_set_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(zinc_tuning)]),
+    "zinc_get_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(zinc_tuning)]),
+    "zinc_autotune": (ctypes.c_int, [_vp, _u32, ctypes.c_char_p, ctypes.POINTER(zinc_tune_result)]),
     "zinc_ntt_forward": (ctypes.c_int, [_vp, _u32, _vp, _u32, _vp]),
     "zinc_ntt_inverse": (ctypes.c_int, [_vp, _u32, _vp, _u32, _vp]),
     "zinc_sample": (ctypes.c_int, [_vp, ctypes.c_int, _u32, _u32, _vp, _u32, _vp, _vp]),
@@ -215,7 +228,27 @@ class Context:
                 "scale": i.scale, "seed": int(i.seed), "cdt": [int(x) for x in i.cdt],
                 "plaintext_bytes": int(i.plaintext_bytes), "ciphertext_bytes": int(i.ciphertext_bytes),
                 "keyed": bool(i.keyed), "precomputed": bool(i.precomputed),
-                "ntt_fp64_mask": int(i.ntt_fp64_mask)}
+                "ntt_fp64_mask": int(i.ntt_fp64_mask), "tile": [int(i.tile[0]), int(i.tile[1])]}
+
+    # -- tuning (speed only; results are identical for every choice) ---------
+    def set_tuning(self, tile_vanilla: int, tile_zinc: int, ntt_fp64_mask: int):
+        t = zinc_tuning()
+        t.tile[0], t.tile[1], t.ntt_fp64_mask = int(tile_vanilla), int(tile_zinc), int(ntt_fp64_mask)
+        _check(load_library().zinc_set_tuning(self.handle, ctypes.byref(t)))
+
+    def get_tuning(self) -> dict:
+        t = zinc_tuning()
+        _check(load_library().zinc_get_tuning(self.handle, ctypes.byref(t)))
+        return {"tile": [int(t.tile[0]), int(t.tile[1])], "ntt_fp64_mask": int(t.ntt_fp64_mask)}
+
+    def autotune(self, batch: int = 512, cache_path: str | None = None) -> dict:
+        r = zinc_tune_result()
+        _check(load_library().zinc_autotune(self.handle, int(batch),
+                                            cache_path.encode() if cache_path else None, ctypes.byref(r)))
+        return {"tile": [int(r.chosen.tile[0]), int(r.chosen.tile[1])],
+                "ntt_fp64_mask": int(r.chosen.ntt_fp64_mask), "from_cache": bool(r.from_cache),
+                "n_timed": int(r.n_timed), "best_ms": [r.best_ms[0], r.best_ms[1]],
+                "default_ms": [r.default_ms[0], r.default_ms[1]]}
 
     # -- the scheme ---------------------------------------------------------
     def keygen(self, stream=None):

@@ -114,6 +114,7 @@ zinc_status zinc_ctx_create(const zinc_params* p, zinc_ctx** out) {
         limbs[l].qinv = (double)(1.0L / (long double)ql);
         limbs[l].fp = force_int || ql >= kFpBound ? 0u : (ql >= kFpNoReduceBound ? 2u : 1u);
         if (limbs[l].fp) c->fp64_mask |= 1u << l;
+        c->h_limbs[l] = limbs[l];
         for (int inv = 0; inv < 2; ++inv) {
             const uint64_t root = inv ? powmod_host(c->psi[l], ql - 2, ql) : c->psi[l];
             pw[0] = 1;
@@ -241,6 +242,8 @@ zinc_status zinc_ctx_info(const zinc_ctx* c, zinc_info* o) {
     o->keyed = c->keyed;
     o->precomputed = c->precomputed;
     o->ntt_fp64_mask = c->fp64_mask;
+    o->tile[0] = c->tile[0];
+    o->tile[1] = c->tile[1];
     return ZINC_OK;
 }
 
@@ -332,6 +335,11 @@ zinc_status zinc_encrypt_slots(zinc_ctx* c, int scheme, const double* slots, uin
     if (n_slots > c->n / 2) return fail(ZINC_E_RANGE, "zinc_encrypt_slots: n_slots exceeds N/2");
     if (zinc_status s = check_batch("zinc_encrypt_slots", batch, {slots, ids, ct})) return s;
     if (batch == 0) return ZINC_OK;
+    const uint32_t tile = c->tile[scheme];
+    if (tile != 16)
+        return launched(launch_encrypt_slots_tile(c->dev, scheme, tile == 8 ? kTileR8 : kTileR32, slots, n_slots,
+                                                  batch, ids, ct, (hipStream_t)stream),
+                        "fused encrypt launch");
     return launched(launch_encrypt_slots(c->dev, scheme, slots, n_slots, batch, ids, ct, (hipStream_t)stream),
                     "fused encrypt launch");
 }

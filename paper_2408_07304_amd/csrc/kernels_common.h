@@ -112,11 +112,12 @@ struct MessageIn {
 // barriers every thread of the workgroup reaches (the whole workgroup, or one
 // of several equal groups running the same ring degree in lockstep).  lds is
 // the group's exchange buffer (LdsWords<N> words), tab the chi table in LDS.
-template <int LOGN, int SCHEME, bool FROM_SLOTS>
-__device__ __forceinline__ void encrypt_item(const DevParams& p, const double* slots, uint32_t n_slots,
-                                             const u64* pt, u64 ct_id, u64* ct, u64* lds, const u64* tab,
-                                             uint32_t t) {
-    using G = typename Cfg<LOGN>::G;
+// G is the thread geometry: any Geom<LOGN, LOGT> with at least 4 coefficients
+// per thread (the default is Cfg<LOGN>::G, 16 per thread).
+template <class G, int SCHEME, bool FROM_SLOTS>
+__device__ __forceinline__ void encrypt_item_g(const DevParams& p, const double* slots, uint32_t n_slots,
+                                               const u64* pt, u64 ct_id, u64* ct, u64* lds, const u64* tab,
+                                               uint32_t t) {
     constexpr int R = G::R, N = G::N, T = G::T;
     const uint32_t L = p.L;
     long long* stash = reinterpret_cast<long long*>(ct + (size_t)(L - 1) * N);
@@ -212,6 +213,13 @@ __device__ __forceinline__ void encrypt_item(const DevParams& p, const double* s
             }
         }
     }
+}
+
+template <int LOGN, int SCHEME, bool FROM_SLOTS>
+__device__ __forceinline__ void encrypt_item(const DevParams& p, const double* slots, uint32_t n_slots,
+                                             const u64* pt, u64 ct_id, u64* ct, u64* lds, const u64* tab,
+                                             uint32_t t) {
+    encrypt_item_g<typename Cfg<LOGN>::G, SCHEME, FROM_SLOTS>(p, slots, n_slots, pt, ct_id, ct, lds, tab, t);
 }
 
 }  // namespace zinc

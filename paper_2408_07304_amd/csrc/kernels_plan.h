@@ -5,11 +5,12 @@
 // groups of N/16 threads which run the same code in lockstep (their barriers
 // coincide), each group with its own slice of the 136 KiB LDS buffer.  Units
 // are ordered by decreasing cost, so the largest ones start first.
+#pragma once
 #include "split_common.h"
 
 namespace zinc {
 
-namespace {
+namespace {  // each including translation unit has its own copy
 
 constexpr int kPlanThreads = 1024;
 constexpr int kPlanLds = LdsWords<16384>::value;     // = 4 x LdsWords<4096> = 2 x LdsWords<8192>
@@ -63,17 +64,15 @@ k_plan(const DevParams* __restrict__ ctxs, const PlanItem* __restrict__ items, c
 
 __global__ void k_reset_counter(uint32_t* counter) { *counter = 0u; }
 
-}  // namespace
-
-hipError_t launch_plan(const PlanDev& d, int scheme, const double* slots, uint64_t* ct, hipStream_t s) {
+// Reset the work counter and run the persistent kernel of one scheme.
+template <int SCHEME>
+hipError_t launch_plan_scheme(const PlanDev& d, const double* slots, uint64_t* ct, hipStream_t s) {
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, d.counter);
-    if (scheme == ZINC_SCHEME_ZINC)
-        hipLaunchKernelGGL(k_plan<ZINC_SCHEME_ZINC>, dim3(d.grid), dim3(kPlanThreads), 0, s, d.ctxs, d.items,
-                           d.units, d.n_units, d.counter, slots, (u64*)ct, (u64*)d.dummy);
-    else
-        hipLaunchKernelGGL(k_plan<ZINC_SCHEME_VANILLA>, dim3(d.grid), dim3(kPlanThreads), 0, s, d.ctxs, d.items,
-                           d.units, d.n_units, d.counter, slots, (u64*)ct, (u64*)d.dummy);
+    hipLaunchKernelGGL(k_plan<SCHEME>, dim3(d.grid), dim3(kPlanThreads), 0, s, d.ctxs, d.items, d.units, d.n_units,
+                       d.counter, slots, (u64*)ct, (u64*)d.dummy);
     return hipGetLastError();
 }
+
+}  // namespace
 
 }  // namespace zinc

@@ -1,0 +1,257 @@
+// Per-context tuning: thread geometry of the fused kernel and NTT arithmetic
+// per limb, chosen by timing every combination, with an on-disk cache.
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "zinc_internal.h"
+
+using namespace zinc;
+
+namespace {
+
+bool tile_ok(uint32_t log_n, uint32_t tile) {
+    if (tile == 16) return true;
+    if (tile == 8) return log_n == 12 || log_n == 13;
+    if (tile == 32) return log_n >= 12 && log_n <= 14;
+    return false;
+}
+
+uint32_t fp_eligible(const zinc_ctx* c) {
+    uint32_t m = 0;
+    for (uint32_t l = 0; l < c->M; ++l)
+        if (c->q[l] < kFpBound) m |= 1u << l;
+    return m;
+}
+
+// Rewrite the limb constants' arithmetic field and upload them.
+zinc_status apply_arith(zinc_ctx* c, uint32_t mask) {
+    for (uint32_t l = 0; l < c->M; ++l) {
+        const uint64_t q = c->q[l];
+        c->h_limbs[l].fp = (mask >> l & 1u) ? (q >= kFpNoReduceBound ? 2u : 1u) : 0u;
+    }
+    const hipError_t e = hipMemcpy(const_cast<LimbConst*>(c->dev.limbs), c->h_limbs, sizeof(LimbConst) * c->M,
+                                   hipMemcpyHostToDevice);
+    if (e != hipSuccess) return plan_fail(ZINC_E_HIP, std::string("limb table upload: ") + hipGetErrorString(e));
+    c->fp64_mask = mask;
+    return ZINC_OK;
+}
+
+std::string cache_key(const zinc_ctx* c, uint32_t batch) {
+    hipDeviceProp_t prop;
+    std::memset(&prop, 0, sizeof(prop));
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipGetDeviceProperties(&prop, dev);
+    std::ostringstream k;
+    std::string arch = prop.gcnArchName;
+    for (char& ch : arch)
+        if (ch == ' ') ch = '_';
+    k << arch << ' ' << prop.multiProcessorCount << ' ' << c->log_n << ' ' << batch << ' ';
+    for (uint32_t l = 0; l < c->M; ++l) k << (l ? "," : "") << c->q[l];
+    return k.str();
+}
+
+// Cache file: one line per result, "zinc-tune-1 <key fields> : <tile_v> <tile_z> <mask>".
+bool cache_lookup(const char* path, const std::string& key, zinc_tuning* t) {
+    std::ifstream f(path);
+    std::string line;
+    const std::string head = "zinc-tune-1 " + key + " : ";
+    while (std::getline(f, line)) {
+        if (line.compare(0, head.size(), head) != 0) continue;
+        std::istringstream v(line.substr(head.size()));
+        zinc_tuning r{};
+        if (v >> r.tile[0] >> r.tile[1] >> r.ntt_fp64_mask) {
+            *t = r;
+            return true;
+        }
+    }
+    return false;
+}
+
+void cache_store(const char* path, const std::string& key, const zinc_tuning& t) {
+    std::vector<std::string> keep;
+    {
+        std::ifstream f(path);
+        std::string line;
+        const std::string head = "zinc-tune-1 " + key + " : ";
+        while (std::getline(f, line))
+            if (!line.empty() && line.compare(0, head.size(), head) != 0) keep.push_back(line);
+    }
+    std::ostringstream o;
+    o << "zinc-tune-1 " << key << " : " << t.tile[0] << ' ' << t.tile[1] << ' ' << t.ntt_fp64_mask;
+    keep.push_back(o.str());
+    const std::string tmp = std::string(path) + ".tmp";
+    {
+        std::ofstream f(tmp, std::ios::trunc);
+        for (const auto& l : keep) f << l << '\n';
+        if (!f) return;   // the cache is an optimisation: failures to write it are ignored
+    }
+    std::rename(tmp.c_str(), path);
+}
+
+struct Bench {
+    zinc_ctx* c;
+    uint32_t batch;
+    double* slots;
+    uint64_t* ids;
+    uint64_t* ct;
+    hipStream_t s;
+    hipEvent_t a, b;
+
+    // Median time of one batch in ms, or a negative value on failure.
+    double time(int scheme) {
+        constexpr int kWarm = 2, kRuns = 5;
+        std::vector<double> ms;
+        for (int i = 0; i < kWarm + kRuns; ++i) {
+            if (hipEventRecord(a, s) != hipSuccess) return -1;
+            if (zinc_encrypt_slots(c, scheme, slots, c->n / 2, batch, ids, ct, s) != ZINC_OK) return -1;
+            if (hipEventRecord(b, s) != hipSuccess || hipEventSynchronize(b) != hipSuccess) return -1;
+            float t = 0;
+            if (hipEventElapsedTime(&t, a, b) != hipSuccess) return -1;
+            if (i >= kWarm) ms.push_back(t);
+        }
+        std::sort(ms.begin(), ms.end());
+        return ms[ms.size() / 2];
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+zinc_status zinc_set_tuning(zinc_ctx* c, const zinc_tuning* t) {
+    if (!c || !t) return plan_fail(ZINC_E_INVAL, "zinc_set_tuning: null argument");
+    for (int s = 0; s < 2; ++s)
+        if (!tile_ok(c->log_n, t->tile[s]) || (c->log_n == 15 && t->tile[s] != 16))
+            return plan_fail(ZINC_E_INVAL, "zinc_set_tuning: tile not available for this ring degree");
+    if (t->ntt_fp64_mask & ~fp_eligible(c))
+        return plan_fail(ZINC_E_INVAL, "zinc_set_tuning: FP64 arithmetic needs a modulus below 2^50");
+    if (t->ntt_fp64_mask != c->fp64_mask) {
+        if (zinc_status st = apply_arith(c, t->ntt_fp64_mask)) return st;
+    }
+    c->tile[0] = t->tile[0];
+    c->tile[1] = t->tile[1];
+    return ZINC_OK;
+}
+
+zinc_status zinc_get_tuning(const zinc_ctx* c, zinc_tuning* t) {
+    if (!c || !t) return plan_fail(ZINC_E_INVAL, "zinc_get_tuning: null argument");
+    *t = zinc_tuning{{c->tile[0], c->tile[1]}, c->fp64_mask, 0u};
+    return ZINC_OK;
+}
+
+zinc_status zinc_autotune(zinc_ctx* c, uint32_t batch, const char* cache_path, zinc_tune_result* out) {
+    if (!c || !out) return plan_fail(ZINC_E_INVAL, "zinc_autotune: null argument");
+    if (batch == 0 || batch > 65536) return plan_fail(ZINC_E_INVAL, "zinc_autotune: batch must be in [1, 65536]");
+    if (!c->keyed) return plan_fail(ZINC_E_STATE, "zinc_autotune before zinc_keygen");
+    std::memset(out, 0, sizeof(*out));
+    const std::string key = cache_key(c, batch);
+    if (cache_path) {
+        zinc_tuning t{};
+        if (cache_lookup(cache_path, key, &t) && zinc_set_tuning(c, &t) == ZINC_OK) {
+            out->chosen = t;
+            out->from_cache = 1;
+            return ZINC_OK;
+        }
+    }
+    const uint32_t eligible = fp_eligible(c), default_mask = c->fp64_mask;
+    std::vector<uint32_t> masks{default_mask};
+    if (default_mask != 0) masks.push_back(0u);
+    if (default_mask != eligible) masks.push_back(eligible);
+    std::vector<uint32_t> tiles;
+    for (uint32_t t : {16u, 8u, 32u})
+        if (tile_ok(c->log_n, t) && (c->log_n != 15 || t == 16)) tiles.push_back(t);
+    const int n_schemes = c->precomputed ? 2 : 1;
+
+    Bench bn{c, batch, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    const size_t b_slots = sizeof(double) * batch * (c->n / 2), b_ids = 8ull * batch;
+    const size_t b_ct = 16ull * batch * c->L * c->n;
+    char* mem = nullptr;
+    hipError_t e = hipMalloc(&mem, b_slots + b_ids + b_ct);
+    if (e != hipSuccess) return plan_fail(ZINC_E_NOMEM, "zinc_autotune: scratch allocation failed");
+    bn.slots = reinterpret_cast<double*>(mem);
+    bn.ids = reinterpret_cast<uint64_t*>(mem + b_slots);
+    bn.ct = reinterpret_cast<uint64_t*>(mem + b_slots + b_ids);
+    e = hipStreamCreateWithFlags(&bn.s, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreate(&bn.a);
+    if (e == hipSuccess) e = hipEventCreate(&bn.b);
+    if (e == hipSuccess) {
+        // slot values uniform on [-1, 1) (a fixed splitmix64 sequence): timing on
+        // zeros would flatter every candidate (lower switching power, higher clocks)
+        std::vector<double> z((size_t)batch * (c->n / 2));
+        uint64_t x = 0x9E3779B97F4A7C15ull;
+        for (double& v : z) {
+            uint64_t r = (x += 0x9E3779B97F4A7C15ull);
+            r = (r ^ (r >> 30)) * 0xBF58476D1CE4E5B9ull;
+            r = (r ^ (r >> 27)) * 0x94D049BB133111EBull;
+            r ^= r >> 31;
+            v = (double)(r >> 11) * 0x1p-52 - 1.0;
+        }
+        e = hipMemcpy(bn.slots, z.data(), b_slots, hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess) {
+        std::vector<uint64_t> ids(batch);
+        for (uint32_t i = 0; i < batch; ++i) ids[i] = i;
+        e = hipMemcpy(bn.ids, ids.data(), b_ids, hipMemcpyHostToDevice);
+    }
+    const uint32_t saved_tile[2] = {c->tile[0], c->tile[1]};
+    zinc_status st = ZINC_OK;
+    double best_total = -1;
+    zinc_tuning best{{saved_tile[0], saved_tile[1]}, default_mask, 0u};
+    if (e != hipSuccess) st = plan_fail(ZINC_E_HIP, std::string("zinc_autotune: setup: ") + hipGetErrorString(e));
+    for (size_t mi = 0; st == ZINC_OK && mi < masks.size(); ++mi) {
+        st = apply_arith(c, masks[mi]);
+        double total = 0;
+        uint32_t pick[2] = {16u, 16u};
+        double pick_ms[2] = {0, 0};
+        for (int sc = 0; st == ZINC_OK && sc < n_schemes; ++sc) {
+            double bm = -1;
+            for (uint32_t t : tiles) {
+                c->tile[sc] = t;
+                const double ms = bn.time(sc);
+                ++out->n_timed;
+                if (ms < 0) {
+                    st = plan_fail(ZINC_E_HIP, "zinc_autotune: timed launch failed");
+                    break;
+                }
+                if (mi == 0 && t == 16) out->default_ms[sc] = ms;
+                if (bm < 0 || ms < bm) {
+                    bm = ms;
+                    pick[sc] = t;
+                }
+            }
+            pick_ms[sc] = bm;
+            total += bm;
+        }
+        if (st == ZINC_OK && (best_total < 0 || total < best_total)) {
+            best_total = total;
+            best = zinc_tuning{{pick[0], n_schemes == 2 ? pick[1] : saved_tile[1]}, masks[mi], 0u};
+            out->best_ms[0] = pick_ms[0];
+            out->best_ms[1] = pick_ms[1];
+        }
+    }
+    if (bn.a) (void)hipEventDestroy(bn.a);
+    if (bn.b) (void)hipEventDestroy(bn.b);
+    if (bn.s) (void)hipStreamDestroy(bn.s);
+    (void)hipFree(mem);
+    if (st != ZINC_OK) {
+        c->tile[0] = saved_tile[0];
+        c->tile[1] = saved_tile[1];
+        (void)apply_arith(c, default_mask);
+        return st;
+    }
+    c->tile[0] = best.tile[0];
+    c->tile[1] = best.tile[1];
+    st = apply_arith(c, best.ntt_fp64_mask);
+    if (st != ZINC_OK) return st;
+    out->chosen = best;
+    if (cache_path) cache_store(cache_path, key, best);
+    return ZINC_OK;
+}
+
+}  // extern "C"

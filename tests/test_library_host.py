@@ -87,6 +87,16 @@ def test_null_arguments_are_rejected(lib):
     assert lib.zinc_decode(None, None, 1, None, None) == zinc.ZINC_E_INVAL
     assert lib.zinc_add(None, None, None, 1, None, None) == zinc.ZINC_E_INVAL
     assert lib.zinc_ctx_destroy(None) == zinc.ZINC_E_INVAL
+    assert lib.zinc_set_tuning(None, None) == zinc.ZINC_E_INVAL
+    assert lib.zinc_get_tuning(None, None) == zinc.ZINC_E_INVAL
+    assert lib.zinc_autotune(None, 1, None, None) == zinc.ZINC_E_INVAL
+    assert lib.zinc_server_create(None, 0, None, ctypes.byref(h)) == zinc.ZINC_E_INVAL
+    assert lib.zinc_server_submit(None, None, None) == zinc.ZINC_E_INVAL
+    assert lib.zinc_server_progress(None, None) == zinc.ZINC_E_INVAL
+    assert lib.zinc_server_query(None, 0, None, None) == zinc.ZINC_E_INVAL
+    assert lib.zinc_server_drain(None) == zinc.ZINC_E_INVAL
+    assert lib.zinc_server_destroy(None) == zinc.ZINC_OK
+    assert lib.zinc_serve_trace(None, 0, None, None, None, 0, None) == zinc.ZINC_E_INVAL
     assert lib.zinc_ctx_info(None, None) == zinc.ZINC_E_INVAL
     assert lib.zinc_ntt_forward(None, 0, None, 1, None) == zinc.ZINC_E_INVAL
     assert lib.zinc_sample(None, 0, 1, 0, None, 1, None, None) == zinc.ZINC_E_INVAL
@@ -98,3 +108,32 @@ def test_single_hip_runtime_in_process(lib):
     one libamdhip64 (two runtimes in one process cannot share a device)."""
     maps = {ln.split()[-1] for ln in open("/proc/self/maps") if "libamdhip64" in ln}
     assert len(maps) == 1, maps
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The binding's ctypes structures have the sizes and field offsets the C
+    compiler gives the header's structures."""
+    import subprocess
+    structs = {"zinc_params": zinc.zinc_params, "zinc_info": zinc.zinc_info, "zinc_item": zinc.zinc_item,
+               "zinc_server_config": zinc.zinc_server_config, "zinc_request": zinc.zinc_request,
+               "zinc_request_times": zinc.zinc_request_times, "zinc_tuning": zinc.zinc_tuning,
+               "zinc_tune_result": zinc.zinc_tune_result}
+    src = ['#include <stdio.h>', '#include <stddef.h>', '#include "zinc.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        src.append(f'printf("{name} size %zu\\n", sizeof({name}));')
+        for f, _ in cls._fields_:
+            src.append(f'printf("{name} {f} %zu\\n", offsetof({name}, {f}));')
+    src.append("return 0; }")
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(src))
+    exe = tmp_path / "layout"
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(root, "include"), str(c), "-o", str(exe)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        n, f, v = line.split()
+        got[(n, f)] = int(v)
+    for name, cls in structs.items():
+        assert got[(name, "size")] == ctypes.sizeof(cls), name
+        for f, _ in cls._fields_:
+            assert got[(name, f)] == getattr(cls, f).offset, (name, f)

@@ -113,6 +113,39 @@ def cpu_baseline(ws, scheme: int, budget_s: float):
                       f"{'Zinc' if scheme == 1 else 'vanilla'} encrypt), {threads} threads, {dt:.1f} s"}
 
 
+def bench_elementwise(ctx, ps, batch: int, steps: int, warmup: int) -> dict:
+    """The element-wise steps alone (Algorithm 1's additions, Eq. 8's products
+    and additions) on `batch` ciphertexts of transform outputs: HBM-bound
+    streams.  Algorithmic bytes per ciphertext: Zinc 32 L N (read the two
+    transforms, write the ciphertext), vanilla 40 L N (plus NTT(u)); the cached
+    Enc(0) and the public key are shared by the batch."""
+    import torch
+
+    L, n = ps.limbs, ps.n
+    hat = torch.randint(0, 2 ** 20, (batch, 2, L, n), dtype=torch.int64, device="cuda")
+    uhat = torch.randint(0, 2 ** 20, (batch, L, n), dtype=torch.int64, device="cuda")
+    out = torch.empty_like(hat)
+    out_d = {}
+    for name, fn, per_ct in (("zinc", lambda: ctx.elementwise_zinc(hat, out), 32 * L * n),
+                             ("vanilla", lambda: ctx.elementwise_vanilla(uhat, hat, out), 40 * L * n)):
+        for _ in range(max(1, warmup)):
+            fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(steps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / steps
+        gbps = batch * per_ct / (ms / 1e3) / 1e9
+        out_d[name] = {"us": ms * 1e3, "algorithmic_bytes": batch * per_ct, "GB_per_s": gbps,
+                       "hbm_frac": gbps * 1e9 / HBM_PEAK_BYTES_PER_S}
+        print(f"[bench] element-wise {name}: {out_d[name]}", file=sys.stderr, flush=True)
+    del hat, uhat, out
+    return out_d
+
+
 def mixed_contexts():
     """Keyed and precomputed contexts of the four mixed-workload parameter sets."""
     import paper_2408_07304_amd as zinc
@@ -315,7 +348,8 @@ def main():
                      "unit": "Gbutterfly/s", "frac": achieved / peak,
                      "ntt_fp64_limbs": [l for l in range(ps.limbs) if (ctx.info()["ntt_fp64_mask"] >> l) & 1],
                      "traffic": traffic_from_profile(ws.name, main_name),
-                     "kernel": ("k_encrypt" if ctx.get_tuning()["tile"][sch] == 16 else "k_encrypt_tile")
+                     "kernel": ("k_encrypt" if ctx.get_tuning()["tile"][sch] == 16
+                                and not (ctx.get_tuning()["reg_epilogue"] >> sch) & 1 else "k_encrypt_tile")
                      + " (fused encode + sample + NTT + add)",
                      "kernel_ms": r["kernel_ms"], "butterflies_per_launch": bfly,
                      "hbm_algorithmic_bytes_per_launch": ws.batch * algorithmic_bytes(ps.n, ps.limbs, ps.slots),
@@ -327,6 +361,7 @@ def main():
         line[f"{name}_kernel_ms"] = res[name]["kernel_ms"]
     if "vanilla" in res and "zinc" in res:
         line["zinc_over_vanilla"] = res["vanilla"]["ms_per_step"] / res["zinc"]["ms_per_step"]
+    line["elementwise"] = bench_elementwise(ctx, ps, ws.batch, args.steps, args.warmup)
     if not args.no_mixed:
         del ct, z
         torch.cuda.empty_cache()

@@ -121,6 +121,7 @@ typedef struct zinc_info {
                                    64-bit integer (Shoup) arithmetic          */
     uint32_t tile[2];           /* coefficients per thread of the fused kernel
                                    for vanilla [0] and Zinc [1] (see zinc_tuning) */
+    uint32_t reg_epilogue;      /* see zinc_tuning                            */
 } zinc_info;
 
 /* Create a context on the current HIP device: validate the parameters, derive
@@ -182,6 +183,22 @@ zinc_status zinc_decrypt(zinc_ctx* ctx, const uint64_t* d_ct, uint32_t batch, ui
  * z_j = Re m(zeta^(5^j)) / Delta.  d_pt [batch][L][N] -> d_slots [batch][N/2]. */
 zinc_status zinc_decode(zinc_ctx* ctx, const uint64_t* d_pt, uint32_t batch, double* d_slots,
                         void* stream);
+
+/* The element-wise step of Zinc encryption alone (Algorithm 1's additions, in
+ * the NTT domain where the cached Enc(0) is kept), for callers that compute
+ * the transforms themselves: d_ct = d_hat + Enc(0) component-wise mod q_l,
+ * with d_hat [batch][2][L][N] = (NTT(m + e1'), NTT(e2')) as canonical residues.
+ * d_ct may be d_hat (in place).  ZINC_E_STATE before zinc_precompute. */
+zinc_status zinc_elementwise_zinc(zinc_ctx* ctx, const uint64_t* d_hat, uint32_t batch, uint64_t* d_ct,
+                                  void* stream);
+
+/* The element-wise step of vanilla encryption alone (Eq. 8 in the NTT domain):
+ * c1 = pk1 * u_hat + hat1, c2 = pk2 * u_hat + hat2 mod q_l, with
+ * d_uhat [batch][L][N] = NTT(u) and d_hat [batch][2][L][N] =
+ * (NTT(m + e1), NTT(e2)), canonical residues.  d_ct may be d_hat; d_uhat must
+ * not overlap d_ct.  ZINC_E_STATE before zinc_keygen. */
+zinc_status zinc_elementwise_vanilla(zinc_ctx* ctx, const uint64_t* d_uhat, const uint64_t* d_hat,
+                                     uint32_t batch, uint64_t* d_ct, void* stream);
 
 /* Homomorphic addition (Eq. 2): out = a + b component-wise mod q_l.
  * All three are [batch][2][L][N]; out may alias a or b. */
@@ -301,12 +318,16 @@ zinc_status zinc_serve_trace(zinc_ctx* const* ctxs, uint32_t n_ctx, const zinc_s
                              zinc_request_times* times);
 
 /* ---- tuning ----------------------------------------------------------------
- * Two per-context choices change speed, never results: every combination
+ * Three per-context choices change speed, never results: every combination
  * gives bit-identical ciphertexts.
  *   tile[s]        coefficients per thread of the fused encode + encrypt kernel
  *                  that zinc_encrypt_slots runs for scheme s (0 vanilla,
  *                  1 Zinc): 16 (default, every N), 8 (N = 4096 and 8192) or 32
  *                  (N <= 16384).  N = 32768 has the single value 16.
+ *   reg_epilogue   bit s set: scheme s stores each transform straight from the
+ *                  registers of its last pass (runs of consecutive
+ *                  coefficients per thread) instead of through LDS in natural
+ *                  order; N <= 16384, with 8 or 16 coefficients per thread.
  *   ntt_fp64_mask  limbs whose forward NTT runs in exact FP64 arithmetic
  *                  instead of 64-bit integer arithmetic; only limbs with a
  *                  modulus below 2^50 may be set (default: all of those).
@@ -315,7 +336,7 @@ zinc_status zinc_serve_trace(zinc_ctx* const* ctxs, uint32_t n_ctx, const zinc_s
 typedef struct zinc_tuning {
     uint32_t tile[2];
     uint32_t ntt_fp64_mask;
-    uint32_t reserved;
+    uint32_t reg_epilogue;
 } zinc_tuning;
 
 typedef struct zinc_tune_result {
@@ -327,11 +348,11 @@ typedef struct zinc_tune_result {
                                    not timed)                                  */
 } zinc_tune_result;
 
-/* ZINC_E_INVAL for a tile the ring degree does not have or a mask bit on a
+/* ZINC_E_INVAL for a form the ring degree does not have or a mask bit on a
  * limb whose modulus is 2^50 or more. */
 zinc_status zinc_set_tuning(zinc_ctx* ctx, const zinc_tuning* t);
 zinc_status zinc_get_tuning(const zinc_ctx* ctx, zinc_tuning* t);
-/* Time every combination of tiles and arithmetic on `batch` (1..65536)
+/* Time every combination of forms and arithmetic on `batch` (1..65536)
  * plaintexts of N/2 slots uniform on [-1, 1) (a fixed pseudo-random sequence)
  * with zinc_encrypt_slots (vanilla, and Zinc when
  * precomputed), on a private stream with HIP events (median of 5 runs after

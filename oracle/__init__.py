@@ -61,8 +61,7 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
-            build()
+        build(force=False)          # (re)compile when missing or older than the C source
         L = ctypes.CDLL(_LIB)
         P = ctypes.POINTER(_Params)
         sigs = {
@@ -86,6 +85,8 @@ def lib():
             "oracle_encrypt_zinc": (None, [P, _u64p, _u64p, ctypes.c_uint64, _u64p]),
             "oracle_decrypt": (None, [P, _u64p, _u64p, _u64p]),
             "oracle_add": (None, [P, _u64p, _u64p, _u64p]),
+            "oracle_elementwise_zinc": (None, [P, _u64p, _u64p, _u64p]),
+            "oracle_elementwise_vanilla": (None, [P, _u64p, _u64p, _u64p, _u64p]),
             "oracle_encode": (None, [P, _f64p, ctypes.c_uint32, _i64p, _f64p]),
             "oracle_decode": (None, [P, _i64p, _f64p]),
             "oracle_to_rns": (None, [P, _i64p, ctypes.c_uint32, _u64p]),
@@ -260,6 +261,27 @@ def encrypt_zinc(P: Params, zero, pt, ct_id: int) -> np.ndarray:
     pt = np.ascontiguousarray(pt, dtype=np.uint64)
     ct = np.zeros((2, P.L, P.n), dtype=np.uint64)
     lib().oracle_encrypt_zinc(P.ref(), _p(zero, _u64p), _p(pt, _u64p), ct_id, _p(ct, _u64p))
+    return ct
+
+
+def elementwise_zinc(P: Params, zero, hat) -> np.ndarray:
+    """Algorithm 1's additions alone, in the NTT domain: [zero + hat]_q, with
+    hat = (NTT(m + e1'), NTT(e2')) as [2][L][N] residues."""
+    zero = np.ascontiguousarray(zero, dtype=np.uint64)
+    hat = np.ascontiguousarray(hat, dtype=np.uint64)
+    ct = np.zeros((2, P.L, P.n), dtype=np.uint64)
+    lib().oracle_elementwise_zinc(P.ref(), _p(zero, _u64p), _p(hat, _u64p), _p(ct, _u64p))
+    return ct
+
+
+def elementwise_vanilla(P: Params, pk, uhat, hat) -> np.ndarray:
+    """Eq. 8's products and additions alone, in the NTT domain:
+    (pk1 u_hat + hat1, pk2 u_hat + hat2) mod q_l over the L data limbs."""
+    pk = np.ascontiguousarray(pk, dtype=np.uint64)
+    uhat = np.ascontiguousarray(uhat, dtype=np.uint64)
+    hat = np.ascontiguousarray(hat, dtype=np.uint64)
+    ct = np.zeros((2, P.L, P.n), dtype=np.uint64)
+    lib().oracle_elementwise_vanilla(P.ref(), _p(pk, _u64p), _p(uhat, _u64p), _p(hat, _u64p), _p(ct, _u64p))
     return ct
 
 

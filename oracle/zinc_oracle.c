@@ -384,6 +384,37 @@ void oracle_encrypt_zinc(const oracle_params* p, const uint64_t* zero, const uin
     free(e1); free(e2); free(mh); free(eh);
 }
 
+/* The element-wise step of Zinc encryption on its own (Algorithm 1, steps 1
+ * and 3, in the NTT domain where the cached zero is kept): given
+ * hat = (NTT(m + e1'), NTT(e2')) as [2][L][N] residues, ct = [zero + hat]_q. */
+void oracle_elementwise_zinc(const oracle_params* p, const uint64_t* zero, const uint64_t* hat, uint64_t* ct) {
+    uint32_t n = 1u << p->log_n, L = p->n_moduli - 1;
+    for (uint32_t j = 0; j < 2; j++)
+        for (uint32_t l = 0; l < L; l++) {
+            size_t o = ((size_t)j * L + l) * n;
+            for (uint32_t k = 0; k < n; k++) ct[o + k] = addmod(zero[o + k], hat[o + k], p->q[l]);
+        }
+}
+
+/* The element-wise step of vanilla encryption on its own (Eq. 8 in the NTT
+ * domain): given u_hat = NTT(u) [L][N] and hat = (NTT(m + e1), NTT(e2)) as
+ * [2][L][N], c1 = [pk1 u_hat + hat1]_q and c2 = [pk2 u_hat + hat2]_q over the
+ * L data limbs (pk [2][M][N]). */
+void oracle_elementwise_vanilla(const oracle_params* p, const uint64_t* pk, const uint64_t* uhat,
+                                const uint64_t* hat, uint64_t* ct) {
+    uint32_t n = 1u << p->log_n, M = p->n_moduli, L = M - 1;
+    for (uint32_t l = 0; l < L; l++) {
+        uint64_t q = p->q[l];
+        const uint64_t* pk1 = pk + (size_t)l * n;
+        const uint64_t* pk2 = pk + ((size_t)M + l) * n;
+        const uint64_t* u = uhat + (size_t)l * n;
+        for (uint32_t k = 0; k < n; k++) {
+            ct[(size_t)l * n + k] = addmod(mulmod(pk1[k], u[k], q), hat[(size_t)l * n + k], q);
+            ct[((size_t)L + l) * n + k] = addmod(mulmod(pk2[k], u[k], q), hat[((size_t)L + l) * n + k], q);
+        }
+    }
+}
+
 /* Decryption (Dec(c) = [c1 + c2 sk]_q): p = INTT(c1 + c2 s_hat) per data limb. */
 void oracle_decrypt(const oracle_params* p, const uint64_t* s_hat, const uint64_t* ct, uint64_t* pt) {
     uint32_t n = 1u << p->log_n, L = p->n_moduli - 1;

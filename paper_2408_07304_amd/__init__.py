@@ -45,11 +45,11 @@ class zinc_info(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("cdt", ctypes.c_uint64 * 38),
                 ("plaintext_bytes", ctypes.c_size_t), ("ciphertext_bytes", ctypes.c_size_t),
                 ("keyed", ctypes.c_int), ("precomputed", ctypes.c_int), ("ntt_fp64_mask", ctypes.c_uint32),
-                ("tile", ctypes.c_uint32 * 2)]
+                ("tile", ctypes.c_uint32 * 2), ("reg_epilogue", ctypes.c_uint32)]
 
 
 class zinc_tuning(ctypes.Structure):
-    _fields_ = [("tile", ctypes.c_uint32 * 2), ("ntt_fp64_mask", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+    _fields_ = [("tile", ctypes.c_uint32 * 2), ("ntt_fp64_mask", ctypes.c_uint32), ("reg_epilogue", ctypes.c_uint32)]
 
 
 class zinc_tune_result(ctypes.Structure):
@@ -100,6 +100,8 @@ _SIGS = {
     "zinc_decrypt": (ctypes.c_int, [_vp, _vp, _u32, _vp, _vp]),
     "zinc_decode": (ctypes.c_int, [_vp, _vp, _u32, _vp, _vp]),
     "zinc_add": (ctypes.c_int, [_vp, _vp, _vp, _u32, _vp, _vp]),
+    "zinc_elementwise_zinc": (ctypes.c_int, [_vp, _vp, _u32, _vp, _vp]),
+    "zinc_elementwise_vanilla": (ctypes.c_int, [_vp, _vp, _vp, _u32, _vp, _vp]),
     "zinc_device_errors": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_uint32)]),
     "zinc_plan_create": (ctypes.c_int, [ctypes.POINTER(_vp), _u32, ctypes.POINTER(zinc_item), _u32,
                                         ctypes.c_int, ctypes.POINTER(_vp)]),
@@ -228,25 +230,29 @@ class Context:
                 "scale": i.scale, "seed": int(i.seed), "cdt": [int(x) for x in i.cdt],
                 "plaintext_bytes": int(i.plaintext_bytes), "ciphertext_bytes": int(i.ciphertext_bytes),
                 "keyed": bool(i.keyed), "precomputed": bool(i.precomputed),
-                "ntt_fp64_mask": int(i.ntt_fp64_mask), "tile": [int(i.tile[0]), int(i.tile[1])]}
+                "ntt_fp64_mask": int(i.ntt_fp64_mask), "tile": [int(i.tile[0]), int(i.tile[1])],
+                "reg_epilogue": int(i.reg_epilogue)}
 
     # -- tuning (speed only; results are identical for every choice) ---------
-    def set_tuning(self, tile_vanilla: int, tile_zinc: int, ntt_fp64_mask: int):
+    def set_tuning(self, tile_vanilla: int, tile_zinc: int, ntt_fp64_mask: int, reg_epilogue: int = 0):
         t = zinc_tuning()
         t.tile[0], t.tile[1], t.ntt_fp64_mask = int(tile_vanilla), int(tile_zinc), int(ntt_fp64_mask)
+        t.reg_epilogue = int(reg_epilogue)
         _check(load_library().zinc_set_tuning(self.handle, ctypes.byref(t)))
 
     def get_tuning(self) -> dict:
         t = zinc_tuning()
         _check(load_library().zinc_get_tuning(self.handle, ctypes.byref(t)))
-        return {"tile": [int(t.tile[0]), int(t.tile[1])], "ntt_fp64_mask": int(t.ntt_fp64_mask)}
+        return {"tile": [int(t.tile[0]), int(t.tile[1])], "ntt_fp64_mask": int(t.ntt_fp64_mask),
+                "reg_epilogue": int(t.reg_epilogue)}
 
     def autotune(self, batch: int = 512, cache_path: str | None = None) -> dict:
         r = zinc_tune_result()
         _check(load_library().zinc_autotune(self.handle, int(batch),
                                             cache_path.encode() if cache_path else None, ctypes.byref(r)))
         return {"tile": [int(r.chosen.tile[0]), int(r.chosen.tile[1])],
-                "ntt_fp64_mask": int(r.chosen.ntt_fp64_mask), "from_cache": bool(r.from_cache),
+                "ntt_fp64_mask": int(r.chosen.ntt_fp64_mask), "reg_epilogue": int(r.chosen.reg_epilogue),
+                "from_cache": bool(r.from_cache),
                 "n_timed": int(r.n_timed), "best_ms": [r.best_ms[0], r.best_ms[1]],
                 "default_ms": [r.default_ms[0], r.default_ms[1]]}
 
@@ -287,6 +293,18 @@ class Context:
 
     def add(self, a, b, out, stream=None):
         _check(load_library().zinc_add(self.handle, _ptr(a), _ptr(b), a.shape[0], _ptr(out), _stream(stream)))
+        return out
+
+    def elementwise_zinc(self, hat, out, stream=None):
+        """Algorithm 1's additions alone: out = hat + Enc(0) (NTT domain)."""
+        _check(load_library().zinc_elementwise_zinc(self.handle, _ptr(hat), hat.shape[0], _ptr(out),
+                                                    _stream(stream)))
+        return out
+
+    def elementwise_vanilla(self, uhat, hat, out, stream=None):
+        """Eq. 8's products and additions alone: out = pk * uhat + hat."""
+        _check(load_library().zinc_elementwise_vanilla(self.handle, _ptr(uhat), _ptr(hat), hat.shape[0],
+                                                       _ptr(out), _stream(stream)))
         return out
 
     def device_errors(self) -> int:

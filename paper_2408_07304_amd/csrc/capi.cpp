@@ -244,6 +244,7 @@ zinc_status zinc_ctx_info(const zinc_ctx* c, zinc_info* o) {
     o->ntt_fp64_mask = c->fp64_mask;
     o->tile[0] = c->tile[0];
     o->tile[1] = c->tile[1];
+    o->reg_epilogue = c->reg_epilogue;
     return ZINC_OK;
 }
 
@@ -336,12 +337,33 @@ zinc_status zinc_encrypt_slots(zinc_ctx* c, int scheme, const double* slots, uin
     if (zinc_status s = check_batch("zinc_encrypt_slots", batch, {slots, ids, ct})) return s;
     if (batch == 0) return ZINC_OK;
     const uint32_t tile = c->tile[scheme];
-    if (tile != 16)
-        return launched(launch_encrypt_slots_tile(c->dev, scheme, tile == 8 ? kTileR8 : kTileR32, slots, n_slots,
-                                                  batch, ids, ct, (hipStream_t)stream),
+    const bool reg = (c->reg_epilogue >> scheme) & 1u;
+    if (tile != 16 || reg)
+        return launched(launch_encrypt_slots_tile(c->dev, scheme, tile == 8 ? kTileR8 : tile == 32 ? kTileR32 : kTileR16,
+                                                  reg, slots, n_slots, batch, ids, ct, (hipStream_t)stream),
                         "fused encrypt launch");
     return launched(launch_encrypt_slots(c->dev, scheme, slots, n_slots, batch, ids, ct, (hipStream_t)stream),
                     "fused encrypt launch");
+}
+
+zinc_status zinc_elementwise_zinc(zinc_ctx* c, const uint64_t* hat, uint32_t batch, uint64_t* ct, void* stream) {
+    if (!c) return fail(ZINC_E_INVAL, "zinc_elementwise_zinc: null context");
+    if (!c->precomputed) return fail(ZINC_E_STATE, "zinc_elementwise_zinc before zinc_precompute");
+    if (zinc_status s = check_batch("zinc_elementwise_zinc", batch, {hat, ct})) return s;
+    if ((uint64_t)batch * 2 * c->L >= (1ull << 31)) return fail(ZINC_E_INVAL, "zinc_elementwise_zinc: batch too large");
+    if (batch == 0) return ZINC_OK;
+    return launched(launch_elementwise_zinc(c->dev, hat, batch, ct, (hipStream_t)stream), "element-wise launch");
+}
+
+zinc_status zinc_elementwise_vanilla(zinc_ctx* c, const uint64_t* uhat, const uint64_t* hat, uint32_t batch,
+                                     uint64_t* ct, void* stream) {
+    if (!c) return fail(ZINC_E_INVAL, "zinc_elementwise_vanilla: null context");
+    if (!c->keyed) return fail(ZINC_E_STATE, "zinc_elementwise_vanilla before zinc_keygen");
+    if (zinc_status s = check_batch("zinc_elementwise_vanilla", batch, {uhat, hat, ct})) return s;
+    if ((uint64_t)batch * c->L >= (1ull << 31)) return fail(ZINC_E_INVAL, "zinc_elementwise_vanilla: batch too large");
+    if (batch == 0) return ZINC_OK;
+    return launched(launch_elementwise_vanilla(c->dev, uhat, hat, batch, ct, (hipStream_t)stream),
+                    "element-wise launch");
 }
 
 zinc_status zinc_decrypt(zinc_ctx* c, const uint64_t* ct, uint32_t batch, uint64_t* pt, void* stream) {

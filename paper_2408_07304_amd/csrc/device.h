@@ -187,7 +187,8 @@ __device__ __forceinline__ uint32_t opaque_tid(uint32_t t) {
     asm volatile("" : "+v"(t));
     return t;
 }
-__device__ __forceinline__ uint32_t opaque_s(uint32_t x) {
+__device__ __forceinline__ uint32_t opaque_s(uint32_t x) {   // x must be wave-uniform
+    x = (uint32_t)__builtin_amdgcn_readfirstlane((int)x);
     asm volatile("" : "+s"(x));
     return x;
 }
@@ -235,6 +236,13 @@ __device__ __forceinline__ void lds_get(const T* lds, T (&v)[G::R], uint32_t t) 
     for (int c = 0; c < G::R; ++c) v[c] = base[pad(G::cpart(P, c))];
 }
 
+// A twiddle and its companion (Shoup factor, or w/q) are adjacent in the
+// tables at an even index: one 16-byte load.
+typedef u64 u64x2 __attribute__((ext_vector_type(2)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ u64x2 load_pair(const u64* p) { return *reinterpret_cast<const u64x2*>(p); }
+__device__ __forceinline__ f64x2 load_pair(const double* p) { return *reinterpret_cast<const f64x2*>(p); }
+
 // ---- integer path (any modulus below 2^60): Shoup butterflies, [0, 4q) ----
 
 template <class G, int P>
@@ -249,7 +257,8 @@ __device__ __forceinline__ void fwd_pass(u64 (&v)[G::R], uint32_t t, const u64* 
         for (int c = 0; c < G::R; ++c) {
             if (c & (1 << b)) continue;
             const uint32_t ti = toff + 2 * tw_index<G, P>(tp, c, b, smul);
-            ct_bfly(v[c], v[c | (1 << b)], tw[ti], tw[ti + 1], q, q2);
+            const u64x2 w = load_pair(tw + ti);
+            ct_bfly(v[c], v[c | (1 << b)], w.x, w.y, q, q2);
         }
     }
 }
@@ -265,7 +274,8 @@ __device__ __forceinline__ void inv_pass(u64 (&v)[G::R], uint32_t t, const u64* 
         for (int c = 0; c < G::R; ++c) {
             if (c & (1 << b)) continue;
             const uint32_t ti = toff + 2 * tw_index<G, P>(tp, c, b, smul);
-            gs_bfly(v[c], v[c | (1 << b)], itw[ti], itw[ti + 1], q, q2);
+            const u64x2 w = load_pair(itw + ti);
+            gs_bfly(v[c], v[c | (1 << b)], w.x, w.y, q, q2);
         }
     }
 }
@@ -396,7 +406,8 @@ __device__ __forceinline__ void fwd_pass_fp(double (&v)[G::R], uint32_t t, const
         for (int c = 0; c < G::R; ++c) {
             if (c & (1 << b)) continue;
             const uint32_t ti = toff + 2 * tw_index<G, P>(tp, c, b, smul);
-            ct_bfly_fp(v[c], v[c | (1 << b)], tw[ti], tw[ti + 1], q);
+            const f64x2 w = load_pair(tw + ti);
+            ct_bfly_fp(v[c], v[c | (1 << b)], w.x, w.y, q);
         }
     }
 }
@@ -524,11 +535,63 @@ __device__ __forceinline__ void fft_dit(C2* A, const double* __restrict__ fft_tw
     }
 }
 
+// The same transform with its stages grouped into passes of LOGR = LOGH -
+// log2(T) stages held in registers.  In pass p, bits [B, B + K) of an index
+// (B = p LOGR, K = min(LOGR, LOGH - B)) come from a thread's register number
+// and the other bits from its thread index (then its remaining register bits):
+// every thread loads its 2^LOGR points, applies the pass's stages and stores
+// them back to the same places, so one barrier per pass suffices.  Every
+// butterfly performs the operations of fft_dit on the same values, so the
+// result equals fft_dit's bit for bit, for any T.  A is indexed through padc().
+__host__ __device__ constexpr uint32_t padc(uint32_t i) { return i + (i >> 4); }
+__host__ __device__ constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x >> 1); }
+
+template <int LOGH, int LOGT, int SIGN, int LOGTAB, int P>
+__device__ __forceinline__ void fft_reg_pass(C2* A, const double* __restrict__ fft_tw, uint32_t t) {
+    constexpr int LOGR = LOGH - LOGT, R = 1 << LOGR;
+    constexpr int B = P * LOGR, K = (LOGH - B < LOGR) ? LOGH - B : LOGR;
+    if constexpr (B < LOGH) {
+        uint32_t idx[R];
+        C2 v[R];
+#pragma unroll
+        for (int e = 0; e < R; ++e) {
+            const uint32_t c = (uint32_t)e & ((1u << K) - 1u), rest = t | ((uint32_t)(e >> K) << LOGT);
+            idx[e] = (rest & ((1u << B) - 1u)) | (c << B) | ((rest >> B) << (B + K));
+            v[e] = A[padc(idx[e])];
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int s = B + k + 1;
+            const uint32_t half = 1u << (s - 1);
+#pragma unroll
+            for (int e = 0; e < R; ++e) {
+                if (e & (1 << k)) continue;
+                const uint32_t ti = (idx[e] & (half - 1u)) << (LOGTAB - s);
+                C2 w{fft_tw[2 * ti], fft_tw[2 * ti + 1]};
+                if (SIGN > 0) w.y = -w.y;
+                const C2 a = v[e], bw = cmul(v[e | (1 << k)], w);
+                v[e] = C2{a.x + bw.x, a.y + bw.y};
+                v[e | (1 << k)] = C2{a.x - bw.x, a.y - bw.y};
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < R; ++e) A[padc(idx[e])] = v[e];
+        __syncthreads();
+        fft_reg_pass<LOGH, LOGT, SIGN, LOGTAB, P + 1>(A, fft_tw, t);
+    }
+}
+
+template <int LOGH, int T, int SIGN, int LOGTAB = LOGH>
+__device__ __forceinline__ void fft_dit_reg(C2* A, const double* __restrict__ fft_tw, uint32_t t) {
+    static_assert((1 << ilog2(T)) == T && ilog2(T) < LOGH, "T must be a power of two below 2^LOGH");
+    fft_reg_pass<LOGH, ilog2(T), SIGN, LOGTAB, 0>(A, fft_tw, t);
+}
+
 // CKKS encoding of one slot vector into the integer coefficients m held in
 // pass-0 layout: place Delta z_j at position (5^j mod 2N - 1)/4 of an N/2-point
 // vector, transform, twist by zeta^-i and scale by 2/N; coefficient i < N/2 is
 // the real part of entry i, coefficient i + N/2 its imaginary part; round half
-// to even.  Uses lds (N words) as the complex work array.
+// to even.  Uses lds (LdsWords<N> words) as the padded complex work array.
 template <class G>
 __device__ __forceinline__ void encode_p0(long long (&m)[G::R], u64* lds, const DevParams& p,
                                           const double* __restrict__ z, uint32_t n_slots, uint32_t t) {
@@ -537,10 +600,10 @@ __device__ __forceinline__ void encode_p0(long long (&m)[G::R], u64* lds, const 
     __syncthreads();
     for (uint32_t j = t; j < (uint32_t)H; j += G::T) {
         const double val = j < n_slots ? p.scale * z[j] : 0.0;
-        A[p.slot_pos[j]] = C2{val, 0.0};
+        A[padc(p.slot_pos[j])] = C2{val, 0.0};
     }
     __syncthreads();
-    fft_dit<LOGH, G::T, -1>(A, p.fft_tw, t);
+    fft_dit_reg<LOGH, G::T, -1>(A, p.fft_tw, t);
     const double f = 2.0 / (double)G::N;
     const uint32_t tp = G::tpart(0, t);
     bool bad = false;
@@ -548,7 +611,7 @@ __device__ __forceinline__ void encode_p0(long long (&m)[G::R], u64* lds, const 
     for (int c = 0; c < G::R; ++c) {
         const uint32_t idx = tp | G::cpart(0, c);
         const uint32_t i = idx & (H - 1);
-        const C2 w = cmul(A[i], C2{p.twist[2 * i], p.twist[2 * i + 1]});
+        const C2 w = cmul(A[padc(i)], C2{p.twist[2 * i], p.twist[2 * i + 1]});
         double x = (idx < (uint32_t)H ? w.x : w.y) * f;
         x = __builtin_rint(x);
         if (!(__builtin_fabs(x) < 4611686018427387904.0)) {   // 2^62 (also catches NaN)

@@ -64,6 +64,29 @@ struct LimbNtt {
         }
     }
 
+    // The same transform, leaving canonical residues in registers: res[c] is
+    // coefficient out_index<G>(t, c).  The last pass covers the lowest index
+    // bits, so a thread holds runs of consecutive coefficients and stores from
+    // registers stay coalesced with no LDS round trip.
+    template <class InInt, class InFp>
+    __device__ __forceinline__ void run_regs(InInt in_int, InFp in_fp, u64 (&res)[G::R]) const {
+        if (fp()) {
+            double v[G::R];
+#pragma unroll
+            for (int c = 0; c < G::R; ++c) v[c] = in_fp(c);
+            ntt_fwd_fp<G>(v, reinterpret_cast<double*>(lds), tw_fp, limb, qd, qinv, mode == 2, t);
+#pragma unroll
+            for (int c = 0; c < G::R; ++c) res[c] = fp_canon(v[c], qd, qinv);
+        } else {
+            u64 v[G::R];
+#pragma unroll
+            for (int c = 0; c < G::R; ++c) v[c] = in_int(c);
+            ntt_fwd<G>(v, lds, tw, limb, q, q2, t);
+#pragma unroll
+            for (int c = 0; c < G::R; ++c) res[c] = canon4(v[c], q, q2);
+        }
+    }
+
     // canonical residue of transform coefficient k (after run())
     __device__ __forceinline__ u64 canon(uint32_t k) const {
         if (fp()) return fp_canon(reinterpret_cast<const double*>(lds)[pad(k)], qd, qinv);
@@ -80,6 +103,45 @@ struct LimbNtt {
         return csub(shoup_lazy(a, b, b_sh, q), q);
     }
 };
+
+// Coefficient index held in register c after the last pass of a transform.
+// The last pass covers index bits from 0, so registers c and c + 1 (c even)
+// hold coefficients k and k + 1 with k even: one 16-byte access.
+template <class G>
+__device__ __forceinline__ uint32_t out_index(uint32_t t, int c) {
+    static_assert(G::LO(G::NPASS - 1) == 0 && G::K(G::NPASS - 1) >= 1, "last pass covers bit 0");
+    return G::tpart(G::NPASS - 1, t) | G::cpart(G::NPASS - 1, c);
+}
+
+__device__ __forceinline__ void store_pair(u64* p, u64 a, u64 b) {
+    *reinterpret_cast<u64x2*>(p) = u64x2{a, b};
+}
+
+// Transform one polynomial of a limb and hand every coefficient pair the
+// thread owns to epi(k, v_k, v_k+1) (k even, canonical values).  REG = false:
+// back to natural order through LDS, so a wave's accesses are contiguous;
+// REG = true: straight from the registers of the last pass, whose runs of
+// consecutive coefficients give 2^K-strided accesses but no LDS round trip.
+// Which is faster depends on the ring degree and the scheme (autotuned).
+template <bool REG, class G, class InInt, class InFp, class Epi>
+__device__ __forceinline__ void transform_store(const LimbNtt<G>& nt, uint32_t t, InInt in_int, InFp in_fp,
+                                                Epi epi) {
+    if constexpr (REG) {
+        u64 r[G::R];
+        nt.run_regs(in_int, in_fp, r);
+        const uint32_t tt = opaque_tid(t);
+#pragma unroll
+        for (int c = 0; c < G::R; c += 2) epi(out_index<G>(tt, c), r[c], r[c + 1]);
+    } else {
+        nt.run(in_int, in_fp);
+        const uint32_t tt = opaque_tid(t);
+#pragma unroll
+        for (int i = 0; i < G::R / 2; ++i) {
+            const uint32_t k = 2 * (tt + G::T * i);
+            epi(k, nt.canon(k), nt.canon(k + 1));
+        }
+    }
+}
 
 // Pass-0 message input of limb l: (m + e) with m read back from the stash
 // (encoded slots) or from the caller's plaintext residues.
@@ -114,11 +176,11 @@ struct MessageIn {
 // the group's exchange buffer (LdsWords<N> words), tab the chi table in LDS.
 // G is the thread geometry: any Geom<LOGN, LOGT> with at least 4 coefficients
 // per thread (the default is Cfg<LOGN>::G, 16 per thread).
-template <class G, int SCHEME, bool FROM_SLOTS>
+template <class G, int SCHEME, bool FROM_SLOTS, bool REG_EPI = false>
 __device__ __forceinline__ void encrypt_item_g(const DevParams& p, const double* slots, uint32_t n_slots,
                                                const u64* pt, u64 ct_id, u64* ct, u64* lds, const u64* tab,
                                                uint32_t t) {
-    constexpr int R = G::R, N = G::N, T = G::T;
+    constexpr int R = G::R, N = G::N;
     const uint32_t L = p.L;
     long long* stash = reinterpret_cast<long long*>(ct + (size_t)(L - 1) * N);
 
@@ -140,30 +202,23 @@ __device__ __forceinline__ void encrypt_item_g(const DevParams& p, const double*
             const LimbNtt<G> nt{p, lc, l, lds, t};
             const MessageIn<G, FROM_SLOTS> msg{stash, pt + (size_t)l * N, e1.fresh(), lc, G::tpart(0, opaque_tid(t))};
             // c1 = zero1 + NTT(m + e1')
-            nt.run([&](int c) { return msg.ri(c); }, [&](int c) { return msg.rf(c); });
-            {
-                const uint32_t tt = opaque_tid(t);
-                const u64* z = p.zero + (size_t)l * N;
-                u64* out = ct + (size_t)l * N;
-#pragma unroll
-                for (int i = 0; i < R; ++i) {
-                    const uint32_t k = tt + T * i;
-                    out[k] = addmod(nt.canon(k), z[k], lc.q);
-                }
-            }
+            const u64* z1 = p.zero + (size_t)l * N;
+            u64* c1 = ct + (size_t)l * N;
+            transform_store<REG_EPI>(nt, t, [&](int c) { return msg.ri(c); }, [&](int c) { return msg.rf(c); },
+                                     [&](uint32_t k, u64 a, u64 b) {
+                                         const u64x2 z = load_pair(z1 + k);
+                                         store_pair(c1 + k, addmod(a, z.x, lc.q), addmod(b, z.y, lc.q));
+                                     });
             // c2 = zero2 + NTT(e2')
             const Packed8<R> e2l = e2.fresh();
-            nt.run([&](int c) { return small_mod(e2l.get(c), lc.q); }, [&](int c) { return (double)e2l.get(c); });
-            {
-                const uint32_t tt = opaque_tid(t);
-                const u64* z = p.zero + (size_t)(L + l) * N;
-                u64* out = ct + (size_t)(L + l) * N;
-#pragma unroll
-                for (int i = 0; i < R; ++i) {
-                    const uint32_t k = tt + T * i;
-                    out[k] = addmod(nt.canon(k), z[k], lc.q);
-                }
-            }
+            const u64* z2 = p.zero + (size_t)(L + l) * N;
+            u64* c2 = ct + (size_t)(L + l) * N;
+            transform_store<REG_EPI>(nt, t, [&](int c) { return small_mod(e2l.get(c), lc.q); },
+                                     [&](int c) { return (double)e2l.get(c); },
+                                     [&](uint32_t k, u64 a, u64 b) {
+                                         const u64x2 z = load_pair(z2 + k);
+                                         store_pair(c2 + k, addmod(a, z.x, lc.q), addmod(b, z.y, lc.q));
+                                     });
         }
     } else {
         Packed8<R> u, e1, e2;
@@ -177,40 +232,34 @@ __device__ __forceinline__ void encrypt_item_g(const DevParams& p, const double*
             const LimbNtt<G> nt{p, lc, l, lds, t};
             u64* c1 = ct + (size_t)l * N;
             u64* c2 = ct + (size_t)(L + l) * N;
-            // u_hat -> the c2 slot of this limb (natural order)
+            // u_hat -> the c2 slot of this limb, at the positions this thread stores
             const Packed8<R> ul = u.fresh();
-            nt.run([&](int c) { return small_mod(ul.get(c), lc.q); }, [&](int c) { return (double)ul.get(c); });
-            {
-                const uint32_t tt = opaque_tid(t);
-#pragma unroll
-                for (int i = 0; i < R; ++i) c2[tt + T * i] = nt.canon(tt + T * i);
-            }
+            transform_store<REG_EPI>(nt, t, [&](int c) { return small_mod(ul.get(c), lc.q); },
+                                     [&](int c) { return (double)ul.get(c); },
+                                     [&](uint32_t k, u64 a, u64 b) { store_pair(c2 + k, a, b); });
             // c1 = pk1 u_hat + NTT(m + e1)
             const MessageIn<G, FROM_SLOTS> msg{stash, pt + (size_t)l * N, e1.fresh(), lc, G::tpart(0, opaque_tid(t))};
-            nt.run([&](int c) { return msg.ri(c); }, [&](int c) { return msg.rf(c); });
-            {
-                const uint32_t tt = opaque_tid(t);
-                const u64* pk = p.pk + (size_t)l * N;
-                const u64* pks = p.pk_sh + (size_t)l * N;
-#pragma unroll
-                for (int i = 0; i < R; ++i) {
-                    const uint32_t k = tt + T * i;
-                    c1[k] = addmod(nt.canon(k), nt.mul(c2[k], pk[k], pks[k]), lc.q);
-                }
-            }
+            const u64* pk1 = p.pk + (size_t)l * N;
+            const u64* pk1s = p.pk_sh + (size_t)l * N;
+            transform_store<REG_EPI>(nt, t, [&](int c) { return msg.ri(c); }, [&](int c) { return msg.rf(c); },
+                                     [&](uint32_t k, u64 a, u64 b) {
+                                         const u64x2 u2 = load_pair(c2 + k), w = load_pair(pk1 + k),
+                                                     ws = load_pair(pk1s + k);
+                                         store_pair(c1 + k, addmod(a, nt.mul(u2.x, w.x, ws.x), lc.q),
+                                                    addmod(b, nt.mul(u2.y, w.y, ws.y), lc.q));
+                                     });
             // c2 = pk2 u_hat + NTT(e2)
             const Packed8<R> e2l = e2.fresh();
-            nt.run([&](int c) { return small_mod(e2l.get(c), lc.q); }, [&](int c) { return (double)e2l.get(c); });
-            {
-                const uint32_t tt = opaque_tid(t);
-                const u64* pk = p.pk + (size_t)(M + l) * N;
-                const u64* pks = p.pk_sh + (size_t)(M + l) * N;
-#pragma unroll
-                for (int i = 0; i < R; ++i) {
-                    const uint32_t k = tt + T * i;
-                    c2[k] = addmod(nt.canon(k), nt.mul(c2[k], pk[k], pks[k]), lc.q);
-                }
-            }
+            const u64* pk2 = p.pk + (size_t)(M + l) * N;
+            const u64* pk2s = p.pk_sh + (size_t)(M + l) * N;
+            transform_store<REG_EPI>(nt, t, [&](int c) { return small_mod(e2l.get(c), lc.q); },
+                                     [&](int c) { return (double)e2l.get(c); },
+                                     [&](uint32_t k, u64 a, u64 b) {
+                                         const u64x2 u2 = load_pair(c2 + k), w = load_pair(pk2 + k),
+                                                     ws = load_pair(pk2s + k);
+                                         store_pair(c2 + k, addmod(a, nt.mul(u2.x, w.x, ws.x), lc.q),
+                                                    addmod(b, nt.mul(u2.y, w.y, ws.y), lc.q));
+                                     });
         }
     }
 }

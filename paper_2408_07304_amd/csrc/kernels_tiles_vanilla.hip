@@ -4,15 +4,17 @@
 
 namespace zinc {
 
-hipError_t launch_encrypt_slots_tile_zinc(const DevParams& p, int tile, const double* slots, uint32_t n_slots,
-                                          uint32_t batch, const uint64_t* ct_ids, uint64_t* ct, hipStream_t s);
+hipError_t launch_encrypt_slots_tile_zinc(const DevParams& p, int tile, bool reg, const double* slots,
+                                          uint32_t n_slots, uint32_t batch, const uint64_t* ct_ids, uint64_t* ct,
+                                          hipStream_t s);
 
-hipError_t launch_encrypt_slots_tile(const DevParams& p, int scheme, int tile, const double* slots,
+hipError_t launch_encrypt_slots_tile(const DevParams& p, int scheme, int tile, bool reg, const double* slots,
                                      uint32_t n_slots, uint32_t batch, const uint64_t* ct_ids, uint64_t* ct,
                                      hipStream_t s) {
-    if (scheme == ZINC_SCHEME_ZINC) return launch_encrypt_slots_tile_zinc(p, tile, slots, n_slots, batch, ct_ids, ct, s);
+    if (scheme == ZINC_SCHEME_ZINC)
+        return launch_encrypt_slots_tile_zinc(p, tile, reg, slots, n_slots, batch, ct_ids, ct, s);
     const EncArgs a{slots, n_slots, nullptr, (const u64*)ct_ids, (u64*)ct};
-    return launch_tile_scheme<ZINC_SCHEME_VANILLA>(p, tile, a, batch, s);
+    return launch_tile_scheme<ZINC_SCHEME_VANILLA>(p, tile, reg, a, batch, s);
 }
 
 }  // namespace zinc

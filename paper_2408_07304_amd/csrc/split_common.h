@@ -74,10 +74,10 @@ __device__ __forceinline__ void encode_split(long long (&mlo)[RS], long long (&m
     for (uint32_t j = t; j < (uint32_t)H; j += TS) {
         const double val = j < n_slots ? p.scale * z[j] : 0.0;
         const uint32_t bk = p.slot_pos[j];               // brv_{log H}(k_j)
-        Ad[2 * (bk & (Q - 1)) + (bk >> (LOGH - 1))] = val;   // Y[k_j / 2] gets Z[k_j] in Re or Im
+        Ad[2 * padc(bk & (Q - 1)) + (bk >> (LOGH - 1))] = val;   // Y[k_j / 2] gets Z[k_j] in Re or Im
     }
     __syncthreads();
-    fft_dit<LOGQ, TS, -1, LOGH>(A, p.fft_tw, t);
+    fft_dit_reg<LOGQ, TS, -1, LOGH>(A, p.fft_tw, t);
     const double f = 2.0 / (double)NF;
     const uint32_t tp0 = GS::tpart(0, t);
     bool bad = false;
@@ -85,7 +85,7 @@ __device__ __forceinline__ void encode_split(long long (&mlo)[RS], long long (&m
     for (int c = 0; c < RS; ++c) {
         const uint32_t i = jp(tp0, c);                   // < H
         const uint32_t m1 = i & (Q - 1), m2 = (Q - m1) & (Q - 1);
-        const C2 y1 = A[m1], y2 = A[m2];
+        const C2 y1 = A[padc(m1)], y2 = A[padc(m2)];
         const C2 ev{0.5 * (y1.x + y2.x), 0.5 * (y1.y - y2.y)};     // (Y1 + conj Y2) / 2
         const C2 od{0.5 * (y1.y + y2.y), -0.5 * (y1.x - y2.x)};    // (Y1 - conj Y2) / 2i
         C2 w{p.fft_tw[2 * (i & (H / 2 - 1))], p.fft_tw[2 * (i & (H / 2 - 1)) + 1]};
@@ -210,7 +210,7 @@ __device__ __forceinline__ void encrypt_item_split(const DevParams& p, const dou
         }
     }
 
-    // message transform of limb l into dst (natural order) with epilogue fn(k, value)
+    // message transform of limb l into dst (natural order) with epilogue epi(k, value)
     auto message_ntt = [&](const SplitLimb& sl, const LimbConst& lc, uint32_t l, const Packed8<RS>& elo,
                            const Packed8<RS>& ehi, u64* dst, auto&& epi) {
         const uint32_t tp0 = GS::tpart(0, opaque_tid(t));

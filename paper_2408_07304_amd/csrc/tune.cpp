@@ -1,5 +1,6 @@
-// Per-context tuning: thread geometry of the fused kernel and NTT arithmetic
-// per limb, chosen by timing every combination, with an on-disk cache.
+// Per-context tuning: form of the fused kernel (thread geometry, epilogue) and
+// NTT arithmetic per limb, chosen by timing every combination, with an
+// on-disk cache.
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
@@ -14,10 +15,12 @@ using namespace zinc;
 
 namespace {
 
-bool tile_ok(uint32_t log_n, uint32_t tile) {
+// Forms of the fused kernel: (coefficients per thread, register epilogue).
+bool form_ok(uint32_t log_n, uint32_t tile, bool reg) {
+    if (log_n == 15) return tile == 16 && !reg;
     if (tile == 16) return true;
     if (tile == 8) return log_n == 12 || log_n == 13;
-    if (tile == 32) return log_n >= 12 && log_n <= 14;
+    if (tile == 32) return !reg;
     return false;
 }
 
@@ -56,16 +59,17 @@ std::string cache_key(const zinc_ctx* c, uint32_t batch) {
     return k.str();
 }
 
-// Cache file: one line per result, "zinc-tune-1 <key fields> : <tile_v> <tile_z> <mask>".
+// Cache file: one line per result,
+// "zinc-tune-2 <key fields> : <tile_v> <tile_z> <mask> <reg_epilogue>".
 bool cache_lookup(const char* path, const std::string& key, zinc_tuning* t) {
     std::ifstream f(path);
     std::string line;
-    const std::string head = "zinc-tune-1 " + key + " : ";
+    const std::string head = "zinc-tune-2 " + key + " : ";
     while (std::getline(f, line)) {
         if (line.compare(0, head.size(), head) != 0) continue;
         std::istringstream v(line.substr(head.size()));
         zinc_tuning r{};
-        if (v >> r.tile[0] >> r.tile[1] >> r.ntt_fp64_mask) {
+        if (v >> r.tile[0] >> r.tile[1] >> r.ntt_fp64_mask >> r.reg_epilogue) {
             *t = r;
             return true;
         }
@@ -78,12 +82,13 @@ void cache_store(const char* path, const std::string& key, const zinc_tuning& t)
     {
         std::ifstream f(path);
         std::string line;
-        const std::string head = "zinc-tune-1 " + key + " : ";
+        const std::string head = "zinc-tune-2 " + key + " : ";
         while (std::getline(f, line))
             if (!line.empty() && line.compare(0, head.size(), head) != 0) keep.push_back(line);
     }
     std::ostringstream o;
-    o << "zinc-tune-1 " << key << " : " << t.tile[0] << ' ' << t.tile[1] << ' ' << t.ntt_fp64_mask;
+    o << "zinc-tune-2 " << key << " : " << t.tile[0] << ' ' << t.tile[1] << ' ' << t.ntt_fp64_mask << ' '
+      << t.reg_epilogue;
     keep.push_back(o.str());
     const std::string tmp = std::string(path) + ".tmp";
     {
@@ -126,9 +131,10 @@ extern "C" {
 
 zinc_status zinc_set_tuning(zinc_ctx* c, const zinc_tuning* t) {
     if (!c || !t) return plan_fail(ZINC_E_INVAL, "zinc_set_tuning: null argument");
+    if (t->reg_epilogue & ~3u) return plan_fail(ZINC_E_INVAL, "zinc_set_tuning: reg_epilogue has bits 0 and 1 only");
     for (int s = 0; s < 2; ++s)
-        if (!tile_ok(c->log_n, t->tile[s]) || (c->log_n == 15 && t->tile[s] != 16))
-            return plan_fail(ZINC_E_INVAL, "zinc_set_tuning: tile not available for this ring degree");
+        if (!form_ok(c->log_n, t->tile[s], (t->reg_epilogue >> s) & 1u))
+            return plan_fail(ZINC_E_INVAL, "zinc_set_tuning: kernel form not available for this ring degree");
     if (t->ntt_fp64_mask & ~fp_eligible(c))
         return plan_fail(ZINC_E_INVAL, "zinc_set_tuning: FP64 arithmetic needs a modulus below 2^50");
     if (t->ntt_fp64_mask != c->fp64_mask) {
@@ -136,12 +142,13 @@ zinc_status zinc_set_tuning(zinc_ctx* c, const zinc_tuning* t) {
     }
     c->tile[0] = t->tile[0];
     c->tile[1] = t->tile[1];
+    c->reg_epilogue = t->reg_epilogue;
     return ZINC_OK;
 }
 
 zinc_status zinc_get_tuning(const zinc_ctx* c, zinc_tuning* t) {
     if (!c || !t) return plan_fail(ZINC_E_INVAL, "zinc_get_tuning: null argument");
-    *t = zinc_tuning{{c->tile[0], c->tile[1]}, c->fp64_mask, 0u};
+    *t = zinc_tuning{{c->tile[0], c->tile[1]}, c->fp64_mask, c->reg_epilogue};
     return ZINC_OK;
 }
 
@@ -163,9 +170,14 @@ zinc_status zinc_autotune(zinc_ctx* c, uint32_t batch, const char* cache_path, z
     std::vector<uint32_t> masks{default_mask};
     if (default_mask != 0) masks.push_back(0u);
     if (default_mask != eligible) masks.push_back(eligible);
-    std::vector<uint32_t> tiles;
+    struct Form {
+        uint32_t tile;
+        bool reg;
+    };
+    std::vector<Form> forms;
     for (uint32_t t : {16u, 8u, 32u})
-        if (tile_ok(c->log_n, t) && (c->log_n != 15 || t == 16)) tiles.push_back(t);
+        for (bool r : {false, true})
+            if (form_ok(c->log_n, t, r)) forms.push_back(Form{t, r});
     const int n_schemes = c->precomputed ? 2 : 1;
 
     Bench bn{c, batch, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -199,30 +211,31 @@ zinc_status zinc_autotune(zinc_ctx* c, uint32_t batch, const char* cache_path, z
         for (uint32_t i = 0; i < batch; ++i) ids[i] = i;
         e = hipMemcpy(bn.ids, ids.data(), b_ids, hipMemcpyHostToDevice);
     }
-    const uint32_t saved_tile[2] = {c->tile[0], c->tile[1]};
+    const uint32_t saved_tile[2] = {c->tile[0], c->tile[1]}, saved_reg = c->reg_epilogue;
     zinc_status st = ZINC_OK;
     double best_total = -1;
-    zinc_tuning best{{saved_tile[0], saved_tile[1]}, default_mask, 0u};
+    zinc_tuning best{{saved_tile[0], saved_tile[1]}, default_mask, saved_reg};
     if (e != hipSuccess) st = plan_fail(ZINC_E_HIP, std::string("zinc_autotune: setup: ") + hipGetErrorString(e));
     for (size_t mi = 0; st == ZINC_OK && mi < masks.size(); ++mi) {
         st = apply_arith(c, masks[mi]);
         double total = 0;
-        uint32_t pick[2] = {16u, 16u};
+        Form pick[2] = {{16u, false}, {16u, false}};
         double pick_ms[2] = {0, 0};
         for (int sc = 0; st == ZINC_OK && sc < n_schemes; ++sc) {
             double bm = -1;
-            for (uint32_t t : tiles) {
-                c->tile[sc] = t;
+            for (const Form& f : forms) {
+                c->tile[sc] = f.tile;
+                c->reg_epilogue = (c->reg_epilogue & ~(1u << sc)) | ((f.reg ? 1u : 0u) << sc);
                 const double ms = bn.time(sc);
                 ++out->n_timed;
                 if (ms < 0) {
                     st = plan_fail(ZINC_E_HIP, "zinc_autotune: timed launch failed");
                     break;
                 }
-                if (mi == 0 && t == 16) out->default_ms[sc] = ms;
+                if (mi == 0 && f.tile == 16 && !f.reg) out->default_ms[sc] = ms;
                 if (bm < 0 || ms < bm) {
                     bm = ms;
-                    pick[sc] = t;
+                    pick[sc] = f;
                 }
             }
             pick_ms[sc] = bm;
@@ -230,7 +243,9 @@ zinc_status zinc_autotune(zinc_ctx* c, uint32_t batch, const char* cache_path, z
         }
         if (st == ZINC_OK && (best_total < 0 || total < best_total)) {
             best_total = total;
-            best = zinc_tuning{{pick[0], n_schemes == 2 ? pick[1] : saved_tile[1]}, masks[mi], 0u};
+            const uint32_t reg = (pick[0].reg ? 1u : 0u) |
+                                 (n_schemes == 2 ? (pick[1].reg ? 2u : 0u) : (saved_reg & 2u));
+            best = zinc_tuning{{pick[0].tile, n_schemes == 2 ? pick[1].tile : saved_tile[1]}, masks[mi], reg};
             out->best_ms[0] = pick_ms[0];
             out->best_ms[1] = pick_ms[1];
         }
@@ -242,11 +257,13 @@ zinc_status zinc_autotune(zinc_ctx* c, uint32_t batch, const char* cache_path, z
     if (st != ZINC_OK) {
         c->tile[0] = saved_tile[0];
         c->tile[1] = saved_tile[1];
+        c->reg_epilogue = saved_reg;
         (void)apply_arith(c, default_mask);
         return st;
     }
     c->tile[0] = best.tile[0];
     c->tile[1] = best.tile[1];
+    c->reg_epilogue = best.reg_epilogue;
     st = apply_arith(c, best.ntt_fp64_mask);
     if (st != ZINC_OK) return st;
     out->chosen = best;

@@ -97,6 +97,7 @@ struct zinc_ctx {
     uint64_t cdt[zinc::kCdtLen] = {};
     uint32_t fp64_mask = 0;       // limbs whose forward NTT uses FP64 arithmetic
     uint32_t tile[2] = {16, 16};  // coefficients per thread of the fused kernel, per scheme
+    uint32_t reg_epilogue = 0;    // bit s: scheme s stores from the last pass's registers
     zinc::LimbConst h_limbs[ZINC_MAX_MODULI] = {};   // host copy of the limb constants
     bool keyed = false, precomputed = false;
     // device allocations owned by the context
@@ -138,10 +139,16 @@ hipError_t launch_ntt(const DevParams& p, bool inverse, uint32_t limb, uint64_t*
 hipError_t launch_sample(const DevParams& p, int kind, uint32_t tag, uint32_t limb,
                          const uint64_t* ct_ids, uint32_t batch, void* out, hipStream_t s);
 
+// element-wise steps alone (kernels_elementwise.hip)
+hipError_t launch_elementwise_zinc(const DevParams& p, const uint64_t* hat, uint32_t batch, uint64_t* ct,
+                                   hipStream_t s);
+hipError_t launch_elementwise_vanilla(const DevParams& p, const uint64_t* uhat, const uint64_t* hat, uint32_t batch,
+                                      uint64_t* ct, hipStream_t s);
+
 // thread geometries of the fused encode + encrypt kernel (coefficients per
 // thread); kTileR16 is the default kernel, the others are kernels_tiles*.hip
 constexpr int kTileR16 = 0, kTileR8 = 1, kTileR32 = 2;
-hipError_t launch_encrypt_slots_tile(const DevParams& p, int scheme, int tile, const double* slots,
+hipError_t launch_encrypt_slots_tile(const DevParams& p, int scheme, int tile, bool reg, const double* slots,
                                      uint32_t n_slots, uint32_t batch, const uint64_t* ct_ids, uint64_t* ct,
                                      hipStream_t s);
 

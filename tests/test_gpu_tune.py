@@ -1,7 +1,8 @@
-"""Tuning (zinc_set_tuning, zinc_autotune): every thread geometry of the fused
-kernel and every choice of NTT arithmetic must give ciphertexts bit-identical
-to the default configuration (which the parity tests tie to the oracle), and
-the autotuner's cache must reproduce its choice without timing."""
+"""Tuning (zinc_set_tuning, zinc_autotune): every form of the fused kernel
+(thread geometry, register or natural-order epilogue) and every choice of NTT
+arithmetic must give ciphertexts bit-identical to the default configuration
+(which the parity tests tie to the oracle), and the autotuner's cache must
+reproduce its choice without timing."""
 import numpy as np
 import pytest
 
@@ -11,7 +12,9 @@ from paper_2408_07304_amd.workloads import PARAM_SETS
 
 pytestmark = pytest.mark.gpu
 
-TILES = {"n4096": (16, 8, 32), "n8192": (16, 8, 32), "n16384": (16, 32), "n32768": (16,)}
+# (coefficients per thread, register epilogue) forms per ring degree
+FORMS = {"n4096": ((16, 0), (16, 1), (8, 0), (8, 1), (32, 0)), "n8192": ((16, 0), (16, 1), (8, 0), (8, 1), (32, 0)),
+         "n16384": ((16, 0), (16, 1), (32, 0)), "n32768": ((16, 0),)}
 
 
 def say(msg):
@@ -38,24 +41,25 @@ def test_every_tile_and_arithmetic_is_bit_identical(name):
     try:
         ref = {s: _encrypt(c, s, z) for s in (zinc.ZINC_SCHEME_VANILLA, zinc.ZINC_SCHEME_ZINC)}
         for mask in masks:
-            for tile in TILES[name]:
-                say(f"{name} tile {tile} fp64 mask {mask:#x}")
-                c.set_tuning(tile, tile, mask)
-                assert c.info()["tile"] == [tile, tile]
+            for tile, reg in FORMS[name]:
+                say(f"{name} tile {tile} register epilogue {reg} fp64 mask {mask:#x}")
+                c.set_tuning(tile, tile, mask, 3 * reg)
+                assert c.info()["tile"] == [tile, tile] and c.info()["reg_epilogue"] == 3 * reg
                 for s in (zinc.ZINC_SCHEME_VANILLA, zinc.ZINC_SCHEME_ZINC):
-                    assert np.array_equal(_encrypt(c, s, z), ref[s]), (tile, mask, s)
+                    assert np.array_equal(_encrypt(c, s, z), ref[s]), (tile, reg, mask, s)
     finally:
-        c.set_tuning(*default["tile"], default["ntt_fp64_mask"])
+        c.set_tuning(*default["tile"], default["ntt_fp64_mask"], default["reg_epilogue"])
 
 
 def test_set_tuning_rejects_unavailable_choices():
     torch_cuda()
-    for name, bad in (("n16384", (8, 16, None)), ("n32768", (32, 16, None)), ("n8192", (16, 16, 1 << 0))):
+    for name, bad in (("n16384", (8, 16, None, 0)), ("n32768", (32, 16, None, 0)), ("n8192", (16, 16, 1 << 0, 0)),
+                      ("n32768", (16, 16, None, 1)), ("n16384", (32, 16, None, 1)), ("n8192", (16, 16, None, 4))):
         c = gpu_ctx(name)
         d = c.get_tuning()
         mask = d["ntt_fp64_mask"] if bad[2] is None else bad[2]       # limb 0 of n8192 is a 60-bit modulus
         with pytest.raises(zinc.ZincError) as e:
-            c.set_tuning(bad[0], bad[1], mask)
+            c.set_tuning(bad[0], bad[1], mask, bad[3])
         assert e.value.status == zinc.ZINC_E_INVAL
         assert c.get_tuning() == d
 
@@ -68,23 +72,26 @@ def test_autotune_and_cache(tmp_path):
     try:
         r = c.autotune(batch=128, cache_path=path)
         say(f"autotune n8192: {r}")
-        assert not r["from_cache"] and r["n_timed"] >= 6
-        assert r["tile"][0] in TILES["n8192"] and r["tile"][1] in TILES["n8192"]
+        chosen = {"tile": r["tile"], "ntt_fp64_mask": r["ntt_fp64_mask"], "reg_epilogue": r["reg_epilogue"]}
+        assert not r["from_cache"] and r["n_timed"] >= 2 * len(FORMS["n8192"])
+        for s in (0, 1):
+            assert (r["tile"][s], (r["reg_epilogue"] >> s) & 1) in FORMS["n8192"]
         assert min(r["best_ms"]) > 0 and min(r["default_ms"]) > 0
         assert r["best_ms"][0] <= r["default_ms"][0] * 1.05 and r["best_ms"][1] <= r["default_ms"][1] * 1.05
-        assert c.get_tuning() == {"tile": r["tile"], "ntt_fp64_mask": r["ntt_fp64_mask"]}
-        c.set_tuning(*d["tile"], d["ntt_fp64_mask"])
+        assert c.get_tuning() == chosen
+        c.set_tuning(*d["tile"], d["ntt_fp64_mask"], d["reg_epilogue"])
         again = c.autotune(batch=128, cache_path=path)
         assert again["from_cache"] and again["n_timed"] == 0
-        assert again["tile"] == r["tile"] and again["ntt_fp64_mask"] == r["ntt_fp64_mask"]
-        assert c.get_tuning() == {"tile": r["tile"], "ntt_fp64_mask": r["ntt_fp64_mask"]}
+        assert {"tile": again["tile"], "ntt_fp64_mask": again["ntt_fp64_mask"],
+                "reg_epilogue": again["reg_epilogue"]} == chosen
+        assert c.get_tuning() == chosen
         lines = open(path).read().splitlines()
-        assert len(lines) == 1 and lines[0].startswith("zinc-tune-1 ")
+        assert len(lines) == 1 and lines[0].startswith("zinc-tune-2 ")
         # the tuned configuration still encrypts identically
         ps = PARAM_SETS["n8192"]
         z = np.random.default_rng(22).uniform(-1, 1, size=(3, ps.slots))
         tuned = _encrypt(c, zinc.ZINC_SCHEME_ZINC, z)
-        c.set_tuning(*d["tile"], d["ntt_fp64_mask"])
+        c.set_tuning(*d["tile"], d["ntt_fp64_mask"], d["reg_epilogue"])
         assert np.array_equal(tuned, _encrypt(c, zinc.ZINC_SCHEME_ZINC, z))
     finally:
-        c.set_tuning(*d["tile"], d["ntt_fp64_mask"])
+        c.set_tuning(*d["tile"], d["ntt_fp64_mask"], d["reg_epilogue"])

@@ -87,6 +87,8 @@ def test_null_arguments_are_rejected(lib):
     assert lib.zinc_decode(None, None, 1, None, None) == zinc.ZINC_E_INVAL
     assert lib.zinc_add(None, None, None, 1, None, None) == zinc.ZINC_E_INVAL
     assert lib.zinc_ctx_destroy(None) == zinc.ZINC_E_INVAL
+    assert lib.zinc_elementwise_zinc(None, None, 1, None, None) == zinc.ZINC_E_INVAL
+    assert lib.zinc_elementwise_vanilla(None, None, None, 1, None, None) == zinc.ZINC_E_INVAL
     assert lib.zinc_set_tuning(None, None) == zinc.ZINC_E_INVAL
     assert lib.zinc_get_tuning(None, None) == zinc.ZINC_E_INVAL
     assert lib.zinc_autotune(None, 1, None, None) == zinc.ZINC_E_INVAL

@@ -193,3 +193,41 @@ def test_round_trip_within_noise_bound(orc, setup):
         mm = orc.crt_centered(P, orc.decrypt(P, sh, ct))
         zz = orc.decode(P, np.array(mm, dtype=np.int64))
         assert np.abs(zz - z).max() < noise_bound(P.n, P.scale)
+
+
+def test_elementwise_steps_compose_to_encryption(orc, setup):
+    """The element-wise steps alone (Algorithm 1's additions; Eq. 8's products
+    and additions), fed with forward NTTs of the same samples, reproduce the
+    whole encryptions, which the identities above pin."""
+    P, sh, pk, zero, s, e = setup
+    for ct_id in (3, 2 ** 33 + 1):
+        m = _message(P, ct_id % 1000)
+        pt = orc.to_rns(P, m)
+
+        def ntt_rows(polys):
+            return np.stack([np.stack([orc.ntt_forward(residues(x, [q])[0], P.log_n, q, P.psi[l])
+                                       for l, q in enumerate(P.data_moduli)]) for x in polys])
+
+        e1z = orc.sample_gaussian(P.seed, ct_id, orc.TAG_E1Z, P.n)
+        e2z = orc.sample_gaussian(P.seed, ct_id, orc.TAG_E2Z, P.n)
+        hat = ntt_rows([m + e1z, e2z])
+        assert np.array_equal(orc.elementwise_zinc(P, zero, hat), orc.encrypt_zinc(P, zero, pt, ct_id))
+
+        u = orc.sample_ternary(P.seed, ct_id, orc.TAG_U, P.n)
+        e1 = orc.sample_gaussian(P.seed, ct_id, orc.TAG_E1, P.n)
+        e2 = orc.sample_gaussian(P.seed, ct_id, orc.TAG_E2, P.n)
+        uhat = ntt_rows([u])[0]
+        hat = ntt_rows([m + e1, e2])
+        assert np.array_equal(orc.elementwise_vanilla(P, pk, uhat, hat), orc.encrypt_vanilla(P, pk, pt, ct_id))
+
+
+def test_elementwise_vanilla_products_decrypt(orc, setup):
+    """With u_hat = NTT(u) and hat = 0, Dec(pk * u_hat) = e u exactly (the
+    public key's own identity, Eq. 7), so the products use pk1 with c1 and pk2
+    with c2."""
+    P, sh, pk, zero, s, e = setup
+    u = orc.sample_ternary(P.seed, 77, orc.TAG_U, P.n)
+    uhat = np.stack([orc.ntt_forward(residues(u, [q])[0], P.log_n, q, P.psi[l])
+                     for l, q in enumerate(P.data_moduli)])
+    ct = orc.elementwise_vanilla(P, pk, uhat, np.zeros((2, P.L, P.n), dtype=np.uint64))
+    assert np.array_equal(orc.decrypt(P, sh, ct), residues(negacyclic(e, u), P.data_moduli))

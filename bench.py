@@ -47,9 +47,11 @@ def peak_bfly_per_s(limbs: int, fp64_mask: int) -> float:
 
 
 HBM_PEAK_BYTES_PER_S = 8.0e12
+# results of zinc_autotune on MI355X, keyed by device, ring degree, moduli and batch
+TUNE_CACHE = os.path.join(ROOT, "paper_2408_07304_amd", "tuning_cache.txt")
 KERNEL_SOURCES = ("paper_2408_07304_amd/csrc/kernels.hip", "paper_2408_07304_amd/csrc/kernels_common.h",
                   "paper_2408_07304_amd/csrc/kernels_tiles.h",
-                  "paper_2408_07304_amd/csrc/device.h")
+                  "paper_2408_07304_amd/csrc/kernels_elementwise.hip", "paper_2408_07304_amd/csrc/device.h")
 
 
 def kernel_hash() -> str:
@@ -81,6 +83,21 @@ def traffic_from_profile(workload: str, scheme_name: str):
     if d.get("kernel_hash") != kernel_hash():
         return None
     return d.get("bytes_per_launch")
+
+
+def elementwise_traffic(workload: str, scheme_name: str):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-kernel scaled) of a
+    standalone element-wise kernel, from the committed PMC summary when it was
+    taken with the current kernel sources, else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_elementwise_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("kernel_hash") != kernel_hash() or scheme_name not in d.get("kernels", {}):
+        return None
+    k = d["kernels"][scheme_name]
+    return k["read_bytes_per_launch"] + k["write_bytes_per_launch"]
 
 
 def cpu_baseline(ws, scheme: int, budget_s: float):
@@ -140,7 +157,8 @@ def bench_elementwise(ctx, ps, batch: int, steps: int, warmup: int) -> dict:
         ms = a.elapsed_time(b) / steps
         gbps = batch * per_ct / (ms / 1e3) / 1e9
         out_d[name] = {"us": ms * 1e3, "algorithmic_bytes": batch * per_ct, "GB_per_s": gbps,
-                       "hbm_frac": gbps * 1e9 / HBM_PEAK_BYTES_PER_S}
+                       "hbm_frac": gbps * 1e9 / HBM_PEAK_BYTES_PER_S,
+                       "traffic": elementwise_traffic(f"n{ps.n}_b{batch}", name)}
         print(f"[bench] element-wise {name}: {out_d[name]}", file=sys.stderr, flush=True)
     del hat, uhat, out
     return out_d
@@ -248,6 +266,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--scheme", choices=["both", "zinc", "vanilla"], default="both")
     ap.add_argument("--no-tune", action="store_true", help="keep the default kernel configuration")
+    ap.add_argument("--tune-cache", default=TUNE_CACHE,
+                    help="autotuning cache file ('' to time every candidate afresh)")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-degree plan and serving measurements")
     ap.add_argument("--serve-requests", type=int, default=10000, help="measured requests of the serving replay")
     ap.add_argument("--serve-warmup", type=int, default=500)
@@ -281,7 +301,9 @@ def main():
     ctx.precompute()
     tune = None
     if not args.no_tune:
-        tune = ctx.autotune(batch=ws.batch)        # thread geometry and NTT arithmetic, outside the timed region
+        # kernel form and NTT arithmetic, outside the timed region; the tuning
+        # cache holds earlier results for this device and parameter set
+        tune = ctx.autotune(batch=ws.batch, cache_path=args.tune_cache or None)
         print(f"[bench] autotune: {tune}", file=sys.stderr, flush=True)
     z = torch.from_numpy(make_slots(ws)).to(dev)
     ids = torch.arange(ws.batch, dtype=torch.int64, device=dev)
@@ -343,7 +365,8 @@ def main():
         "config": {"workload": ws.name, "N": ps.n, "moduli_bits": list(ps.bits), "data_limbs": ps.limbs,
                    "scale_log2": int(math.log2(ps.scale)), "batch": ws.batch, "slots": ps.slots,
                    "slot_values": ws.dist, "scheme": main_name, "fused_encode": True,
-                   "tuning": ctx.get_tuning(), "autotuned": tune is not None},
+                   "tuning": ctx.get_tuning(), "autotuned": tune is not None,
+                   "tuning_from_cache": bool(tune and tune["from_cache"])},
         "roofline": {"bound": "alu", "achieved": achieved / 1e9, "peak": peak / 1e9,
                      "unit": "Gbutterfly/s", "frac": achieved / peak,
                      "ntt_fp64_limbs": [l for l in range(ps.limbs) if (ctx.info()["ntt_fp64_mask"] >> l) & 1],

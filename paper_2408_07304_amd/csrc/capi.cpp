@@ -149,8 +149,9 @@ zinc_status zinc_ctx_create(const zinc_params* p, zinc_ctx** out) {
         slot_pos[j] = bitrev((uint32_t)((g - 1) / 4), logh);
         g = g * 5 % two_n;
     }
-    uint64_t cdt[kCdtPad];
+    uint64_t cdt[kCdtTab];
     for (int i = 0; i < kCdtPad; ++i) cdt[i] = i < kCdtLen ? c->cdt[i] : ~0ull;
+    gaussian_buckets(c->cdt, cdt + kCdtPad);
 
     // ---- one device block ----
     const size_t nb = (size_t)n * 8, L = c->L;
@@ -159,7 +160,7 @@ zinc_status zinc_ctx_create(const zinc_params* p, zinc_ctx** out) {
     const size_t o_limbs = take(sizeof(LimbConst) * M);
     const size_t o_tw = take(nb * 2 * M), o_itw = take(nb * 2 * M), o_twfp = take(nb * 2 * M);
     const size_t o_fft = take(sizeof(double) * H), o_twist = take(sizeof(double) * 2 * H);
-    const size_t o_pos = take(4 * H), o_cdt = take(8 * kCdtPad);
+    const size_t o_pos = take(4 * H), o_cdt = take(8 * kCdtTab);
     const size_t o_sk = take(nb * M), o_sks = take(nb * M);
     const size_t o_pk = take(nb * 2 * M), o_pks = take(nb * 2 * M);
     const size_t o_zero = take(nb * 2 * L), o_err = take(256);
@@ -175,7 +176,7 @@ zinc_status zinc_ctx_create(const zinc_params* p, zinc_ctx** out) {
         {o_itw, itw.data(), nb * 2 * M}, {o_twfp, tw_fp.data(), nb * 2 * M},
         {o_fft, fft_tw.data(), sizeof(double) * H},
         {o_twist, twist.data(), sizeof(double) * 2 * H}, {o_pos, slot_pos.data(), 4 * H},
-        {o_cdt, cdt, 8 * kCdtPad}};
+        {o_cdt, cdt, 8 * kCdtTab}};
     for (const Up& u : ups) {
         e = hipMemcpy(base + u.o, u.src, u.bytes, hipMemcpyHostToDevice);
         if (e != hipSuccess) {

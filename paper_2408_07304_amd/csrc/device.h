@@ -111,19 +111,11 @@ __device__ __forceinline__ U4 draw(u64 seed, u64 ct_id, uint32_t tag, uint32_t l
                   (uint32_t)(ct_id >> 32), (uint32_t)seed, (uint32_t)(seed >> 32));
 }
 
-// chi: x = -19 + #{i < 38 : U >= T[i]}; branch-free scan of the table.
-__device__ __forceinline__ int gauss_from(u64 u, const u64* __restrict__ cdt) {
-    int cnt = 0;
-#pragma unroll
-    for (int i = 0; i < kCdtLen; ++i) cnt += (u >= cdt[i]) ? 1 : 0;
-    return cnt - kTail;
-}
-
-// The same count by a branch-free binary search over the table padded to 64
-// entries with 2^64-1 (tab in LDS, ascending).  After the six steps pos is the
-// number of entries <= u, except that it stops at 63; the pads can only be
-// <= u when u = 2^64-1, where every real threshold is counted, so the count of
-// real thresholds is min(pos, 38).
+// chi: x = -19 + #{i < 38 : U >= T[i]}, the count by a branch-free binary
+// search over the table padded to 64 entries with 2^64-1 (tab in LDS,
+// ascending).  After the six steps pos is the number of entries <= u, except
+// that it stops at 63; the pads can only be <= u when u = 2^64-1, where every
+// real threshold is counted, so the count of real thresholds is min(pos, 38).
 __device__ __forceinline__ int gauss_bsearch(u64 u, const u64* tab) {
     uint32_t pos = 0;
 #pragma unroll
@@ -131,9 +123,22 @@ __device__ __forceinline__ int gauss_bsearch(u64 u, const u64* tab) {
     return (int)(pos < (uint32_t)kCdtLen ? pos : (uint32_t)kCdtLen) - kTail;
 }
 
-// Copy the padded table into LDS (one entry per thread of the first 64).
+// The same value with one lookup in the bucket table that follows the
+// thresholds in tab (built by the host's gaussian_buckets): within bucket
+// b = u >> 56 all but the two tail buckets hold at most one threshold above
+// the bucket's start, which is compared in full 64 bits; the tail buckets,
+// flagged in bit 63, fall back to the search.
+__device__ __forceinline__ int gauss_sample(u64 u, const u64* tab) {
+    const u64 e = tab[kCdtPad + (uint32_t)(u >> 56)];
+    const u64 thr = (u & 0xFF00000000000000ull) | (e & 0x00FFFFFFFFFFFFFFull);
+    int x = (int)((e >> 56) & 63u) + (u >= thr ? 1 : 0) - kTail;
+    if (e >> 63) x = gauss_bsearch(u, tab);
+    return x;
+}
+
+// Copy the sampler's table (kCdtTab words) to LDS; blockDim.x threads.
 __device__ __forceinline__ void load_cdt(u64* tab, const u64* __restrict__ cdt, uint32_t t) {
-    if (t < (uint32_t)kCdtPad) tab[t] = cdt[t];
+    for (uint32_t i = t; i < (uint32_t)kCdtTab; i += blockDim.x) tab[i] = cdt[i];
     __syncthreads();
 }
 
@@ -478,8 +483,8 @@ __device__ __forceinline__ void sample_gauss_p0(Packed8<G::R>& out, const DevPar
         if (c & TOP) continue;
         const uint32_t k = tp | G::cpart(0, c);   // < N/2
         const U4 r = draw(p.seed, ct_id, tag, 0, k);
-        out.set(c, gauss_bsearch((u64)r.x | ((u64)r.y << 32), tab));
-        out.set(c | TOP, gauss_bsearch((u64)r.z | ((u64)r.w << 32), tab));
+        out.set(c, gauss_sample((u64)r.x | ((u64)r.y << 32), tab));
+        out.set(c | TOP, gauss_sample((u64)r.z | ((u64)r.w << 32), tab));
     }
 }
 

@@ -136,4 +136,26 @@ void gaussian_cdt(double sigma, uint64_t out[kCdtLen]) {
     }
 }
 
+// First-level table of the chi sampler.  For a 64-bit uniform U in bucket
+// b = U >> 56 the count #{i : U >= T[i]} is lo_b + #{i : b 2^56 < T[i] <= U},
+// lo_b = #{i : T[i] <= b 2^56}.  Entry b: bits [0, 56) the low bits of the
+// bucket's one interior threshold (0 if it has none), bits [56, 62) the base
+// count (lo_b, or lo_b - 1 without an interior threshold, so that the one
+// comparison U >= (b << 56 | low bits) always adds 1), bit 63 set when the
+// bucket holds two or more interior thresholds (the device then searches the
+// whole table).
+void gaussian_buckets(const uint64_t cdt[kCdtLen], uint64_t out[kCdtBuckets]) {
+    for (int b = 0; b < kCdtBuckets; ++b) {
+        const uint64_t start = (uint64_t)b << 56;
+        uint64_t lo = 0, inner = 0, thr = 0;
+        for (int i = 0; i < kCdtLen; ++i) {
+            if (cdt[i] <= start) ++lo;
+            else if ((cdt[i] >> 56) == (uint64_t)b) { ++inner; thr = cdt[i]; }
+        }
+        if (inner == 1) out[b] = (lo << 56) | (thr & ((1ull << 56) - 1));
+        else if (inner == 0 && lo > 0) out[b] = (lo - 1) << 56;
+        else out[b] = 1ull << 63;
+    }
+}
+
 }  // namespace zinc

@@ -19,7 +19,7 @@ k_encrypt(DevParams p, EncArgs a) {
     using G = typename Cfg<LOGN>::G;
     constexpr int N = G::N;
     __shared__ u64 lds[LdsWords<N>::value];
-    __shared__ u64 tab[kCdtPad];
+    __shared__ u64 tab[kCdtTab];
     const uint32_t t = threadIdx.x;
     const uint32_t b = blockIdx.x;
     load_cdt(tab, p.cdt, t);
@@ -38,7 +38,7 @@ __global__ void __launch_bounds__(Cfg<LOGN>::G::T) k_keygen(DevParams p, u64* sk
     using G = typename Cfg<LOGN>::G;
     constexpr int R = G::R, N = G::N;
     __shared__ u64 lds[LdsWords<N>::value];
-    __shared__ u64 tab[kCdtPad];
+    __shared__ u64 tab[kCdtTab];
     const uint32_t t = threadIdx.x;
     const uint32_t l = blockIdx.x;
     load_cdt(tab, p.cdt, t);
@@ -224,6 +224,8 @@ __global__ void __launch_bounds__(Cfg<LOGN>::G::T) k_ntt(DevParams p, uint32_t l
 
 __global__ void __launch_bounds__(256) k_sample(DevParams p, int kind, uint32_t tag, uint32_t limb,
                                                 const u64* ct_ids, void* out) {
+    __shared__ u64 tab[kCdtTab];
+    load_cdt(tab, p.cdt, threadIdx.x);
     const uint32_t n = p.n, b = blockIdx.y;
     const u64 id = ct_ids[b];
     for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
@@ -234,7 +236,7 @@ __global__ void __launch_bounds__(256) k_sample(DevParams p, int kind, uint32_t 
         } else if (kind == 1) {
             const U4 r = draw(p.seed, id, tag, 0, k % (n / 2));
             const u64 uu = (k / (n / 2)) ? ((u64)r.z | ((u64)r.w << 32)) : ((u64)r.x | ((u64)r.y << 32));
-            reinterpret_cast<long long*>(out)[(size_t)b * n + k] = gauss_from(uu, p.cdt);
+            reinterpret_cast<long long*>(out)[(size_t)b * n + k] = gauss_sample(uu, tab);
         } else {
             const u64 q = p.limbs[limb].q;
             const U4 r = draw(p.seed, id, tag, limb, k);

@@ -34,7 +34,7 @@ __global__ void __launch_bounds__(kPlanThreads) __attribute__((amdgpu_waves_per_
 k_plan(const DevParams* __restrict__ ctxs, const PlanItem* __restrict__ items, const PlanUnit* __restrict__ units,
        uint32_t n_units, uint32_t* counter, const double* __restrict__ slots, u64* ct, u64* dummy) {
     __shared__ u64 lds[kPlanLds];
-    __shared__ u64 tab[kCdtPad];
+    __shared__ u64 tab[kCdtTab];
     __shared__ uint32_t s_unit;
     const uint32_t t = threadIdx.x;
     for (;;) {

@@ -17,7 +17,7 @@ template <int SCHEME, bool FROM_SLOTS>
 __global__ void __launch_bounds__(TS) __attribute__((amdgpu_waves_per_eu(4)))
 k_encrypt_split(DevParams p, EncArgs a) {
     __shared__ u64 lds[LdsWords<NH>::value];
-    __shared__ u64 tab[kCdtPad];
+    __shared__ u64 tab[kCdtTab];
     const uint32_t t = threadIdx.x, b = blockIdx.x;
     load_cdt(tab, p.cdt, t);
     const uint32_t L = p.L;
@@ -30,7 +30,7 @@ k_encrypt_split(DevParams p, EncArgs a) {
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(TS) k_keygen_split(DevParams p, u64* sk, u64* sk_sh, u64* pk, u64* pk_sh) {
     __shared__ u64 lds[LdsWords<NH>::value];
-    __shared__ u64 tab[kCdtPad];
+    __shared__ u64 tab[kCdtTab];
     const uint32_t t = threadIdx.x, l = blockIdx.x;
     load_cdt(tab, p.cdt, t);
     LimbConst lc = p.limbs[l];

@@ -18,7 +18,7 @@ __global__ void __launch_bounds__(G::T) __attribute__((amdgpu_waves_per_eu(WPE))
 k_encrypt_tile(DevParams p, EncArgs a) {
     constexpr int N = G::N;
     __shared__ u64 lds[LdsWords<N>::value];
-    __shared__ u64 tab[kCdtPad];
+    __shared__ u64 tab[kCdtTab];
     const uint32_t t = threadIdx.x;
     const uint32_t b = blockIdx.x;
     load_cdt(tab, p.cdt, t);

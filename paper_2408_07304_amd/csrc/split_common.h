@@ -33,8 +33,8 @@ __device__ __forceinline__ void sample_gauss_split(Pair8& o, const DevParams& p,
 #pragma unroll
     for (int c = 0; c < RS; ++c) {
         const U4 r = draw(p.seed, ct_id, tag, 0, jp(tp0, c));
-        o.lo.set(c, gauss_bsearch((u64)r.x | ((u64)r.y << 32), tab));
-        o.hi.set(c, gauss_bsearch((u64)r.z | ((u64)r.w << 32), tab));
+        o.lo.set(c, gauss_sample((u64)r.x | ((u64)r.y << 32), tab));
+        o.hi.set(c, gauss_sample((u64)r.z | ((u64)r.w << 32), tab));
     }
 }
 

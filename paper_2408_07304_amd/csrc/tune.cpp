@@ -15,6 +15,10 @@ using namespace zinc;
 
 namespace {
 
+// A candidate replaces an earlier (preferred) one only if it is faster by more
+// than this fraction, so that near-ties resolve the same way run after run.
+constexpr double kMinGain = 0.01;
+
 // Forms of the fused kernel: (coefficients per thread, register epilogue).
 bool form_ok(uint32_t log_n, uint32_t tile, bool reg) {
     if (log_n == 15) return tile == 16 && !reg;
@@ -233,7 +237,9 @@ zinc_status zinc_autotune(zinc_ctx* c, uint32_t batch, const char* cache_path, z
                     break;
                 }
                 if (mi == 0 && f.tile == 16 && !f.reg) out->default_ms[sc] = ms;
-                if (bm < 0 || ms < bm) {
+                // candidates come in order of preference (default form first);
+                // a later one must be faster by more than the timing noise
+                if (bm < 0 || ms < bm * (1.0 - kMinGain)) {
                     bm = ms;
                     pick[sc] = f;
                 }
@@ -241,7 +247,7 @@ zinc_status zinc_autotune(zinc_ctx* c, uint32_t batch, const char* cache_path, z
             pick_ms[sc] = bm;
             total += bm;
         }
-        if (st == ZINC_OK && (best_total < 0 || total < best_total)) {
+        if (st == ZINC_OK && (best_total < 0 || total < best_total * (1.0 - kMinGain))) {
             best_total = total;
             const uint32_t reg = (pick[0].reg ? 1u : 0u) |
                                  (n_schemes == 2 ? (pick[1].reg ? 2u : 0u) : (saved_reg & 2u));

@@ -13,6 +13,8 @@ namespace zinc {
 
 constexpr int kCdtLen = 38;       // support [-19, 19] -> 38 thresholds
 constexpr int kCdtPad = 64;       // padded to a power of two for the device search
+constexpr int kCdtBuckets = 256;  // first-level table over the top 8 bits of the uniform
+constexpr int kCdtTab = kCdtPad + kCdtBuckets;   // words of the device table
 constexpr int kTail = 19;
 
 enum Tag : uint32_t { TAG_SK = 1, TAG_A = 2, TAG_EPK = 3, TAG_U = 4, TAG_E1 = 5, TAG_E2 = 6,
@@ -48,7 +50,7 @@ struct DevParams {
     const double* fft_tw;         // [N/4][2]   exp(-2 pi i k / (N/2)), k < N/4
     const double* twist;          // [N/2][2]   exp(-i pi k / N),       k < N/2
     const uint32_t* slot_pos;     // [N/2]      brv_{log N - 1}((5^j mod 2N - 1) / 4)
-    const uint64_t* cdt;          // [kCdtPad]  cumulative table, padded with 2^64-1
+    const uint64_t* cdt;          // [kCdtTab]  cumulative table padded with 2^64-1, then bucket entries
     const uint64_t* sk;           // [M][N]     s_hat
     const uint64_t* sk_sh;        // [M][N]     Shoup companions of s_hat
     const uint64_t* pk;           // [2][M][N]
@@ -115,6 +117,7 @@ uint64_t mulmod_host(uint64_t a, uint64_t b, uint64_t q);
 uint64_t powmod_host(uint64_t b, uint64_t e, uint64_t q);
 uint64_t shoup_companion(uint64_t w, uint64_t q);
 void gaussian_cdt(double sigma, uint64_t out[kCdtLen]);
+void gaussian_buckets(const uint64_t cdt[kCdtLen], uint64_t out[kCdtBuckets]);
 
 void set_error(const std::string& msg);
 

@@ -164,6 +164,57 @@ def bench_elementwise(ctx, ps, batch: int, steps: int, warmup: int) -> dict:
     return out_d
 
 
+# Total encryption times the paper reports for its datasets (Table 2; SEAL,
+# one thread of an EPYC 7302P, N = 32768): context, not a target.
+PAPER_TABLE2_S = {"covid19": {"ckks": 19.2, "zinc": 8.2}, "bitcoin": {"ckks": 62.2, "zinc": 24.8},
+                  "hg38": {"ckks": 1983.6, "zinc": 812.6}}
+
+
+def bench_table2(chunk: int = 1024, reps: int = 2) -> dict:
+    """The paper's parameters (N = 32768, 16 primes, Delta = 2^55) on
+    synthetic rows shaped like its three datasets: one ciphertext per row,
+    fused encode + encrypt in launches of `chunk` rows into one reused output
+    buffer; total time for the whole dataset."""
+    import torch
+
+    import paper_2408_07304_amd as zinc
+    from paper_2408_07304_amd.workloads import P32768_Q16, TABLE2, dataset_rows
+
+    ps = P32768_Q16
+    ctx = zinc.context_for(ps)
+    ctx.keygen()
+    ctx.precompute()
+    ct = torch.empty((chunk, 2, ps.limbs, ps.n), dtype=torch.int64, device="cuda")
+    out = {"params": {"N": ps.n, "moduli_bits": list(ps.bits), "scale_log2": 55}, "chunk": chunk, "reps": reps}
+    for d in TABLE2:
+        z = torch.from_numpy(dataset_rows(d, 0, d.rows)).to("cuda")
+        ids = torch.arange(d.rows, dtype=torch.int64, device="cuda")
+        r = {"rows": d.rows, "slots_per_row": d.slots}
+        for name, sch in (("zinc", 1), ("vanilla", 0)):
+            def run():
+                for s0 in range(0, d.rows, chunk):
+                    n = min(chunk, d.rows - s0)
+                    ctx.encrypt_slots(sch, z[s0:s0 + n], ids[s0:s0 + n], ct[:n])
+            ctx.encrypt_slots(sch, z[:1], ids[:1], ct[:1])
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(reps):
+                run()
+            b.record()
+            torch.cuda.synchronize()
+            r[f"{name}_s"] = a.elapsed_time(b) / reps / 1e3
+        r["zinc_over_vanilla"] = r["vanilla_s"] / r["zinc_s"]
+        r["paper_seal_cpu_s"] = PAPER_TABLE2_S[d.name]
+        out[d.name] = r
+        print(f"[bench] table-2 shape {d.name}: {r}", file=sys.stderr, flush=True)
+        del z, ids
+    ctx.close()
+    del ct
+    torch.cuda.empty_cache()
+    return out
+
+
 def mixed_contexts():
     """Keyed and precomputed contexts of the four mixed-workload parameter sets."""
     import paper_2408_07304_amd as zinc
@@ -266,6 +317,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--scheme", choices=["both", "zinc", "vanilla"], default="both")
     ap.add_argument("--no-tune", action="store_true", help="keep the default kernel configuration")
+    ap.add_argument("--no-table2", action="store_true",
+                    help="skip the paper-parameter runs on rows shaped like its datasets")
     ap.add_argument("--tune-cache", default=TUNE_CACHE,
                     help="autotuning cache file ('' to time every candidate afresh)")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-degree plan and serving measurements")
@@ -396,6 +449,8 @@ def main():
                                             args.serve_budget_gib)
         for c in mctx:
             c.close()
+    if not args.no_table2:
+        line["table2_shapes"] = bench_table2()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(ws, sch, args.cpu_budget)
     print(json.dumps(line), flush=True)

@@ -52,7 +52,12 @@ P16384 = ParamSet("n16384", 14, (60, 50, 50, 50, 50, 50, 50, 60), 2.0 ** 50)
 # (the paper's ring degree and scale; System Implementation section).
 P32768 = ParamSet("n32768", 15, (55,) * 15, 2.0 ** 55)
 
-PARAM_SETS = {p.name: p for p in (P4096, P8192, P16384, P32768)}
+# The paper's own parameters (System Implementation section): N = 32768 and a
+# 881-bit chain of 16 primes near 2^55, the last near 2^56 (15 data limbs plus
+# the special prime here), Delta = 2^55.
+P32768_Q16 = ParamSet("n32768_q16", 15, (55,) * 15 + (56,), 2.0 ** 55)
+
+PARAM_SETS = {p.name: p for p in (P4096, P8192, P16384, P32768, P32768_Q16)}
 
 
 @dataclass(frozen=True)
@@ -69,6 +74,31 @@ W_MAIN = Workload("n8192_b1024", (P8192,), 1024, "uniform", 2)
 W_LARGE = Workload("n16384_b4096", (P16384,), 4096, "gauss_clip8", 3)
 W_MIXED = Workload("mixed_b2048", (P4096, P8192, P16384, P32768), 2048, "uniform", 4)
 WORKLOADS = {w.name: w for w in (W_SMALL, W_MAIN, W_LARGE, W_MIXED)}
+
+
+@dataclass(frozen=True)
+class DatasetShape:
+    """Shape of one of the paper's evaluation datasets (Experimental Setup
+    section): one ciphertext per row, `slots` values per row.  The datasets
+    themselves are not available; rows are filled with uniform [-1, 1)
+    values (their value distributions are not stated either)."""
+    name: str
+    rows: int
+    slots: int
+    data_seed: int
+
+
+# 341 days x 16 metrics; 1,086 trade volumes; 34,424 rows whose attribute count
+# the paper does not give (three are named: transcription positions, coding
+# regions, number of exons), read here as 3 values per row.
+TABLE2 = (DatasetShape("covid19", 341, 16, 6), DatasetShape("bitcoin", 1086, 1, 7),
+          DatasetShape("hg38", 34424, 3, 8))
+
+
+def dataset_rows(d: DatasetShape, first: int, count: int) -> np.ndarray:
+    """float64 [count][d.slots] values of rows first .. first + count - 1."""
+    rng = np.random.default_rng([d.data_seed, first])
+    return rng.uniform(-1.0, 1.0, size=(count, d.slots))
 
 
 def slot_values(rng: np.random.Generator, count: int, n_slots: int, dist: str) -> np.ndarray:

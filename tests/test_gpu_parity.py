@@ -12,11 +12,12 @@ import pytest
 import oracle
 import paper_2408_07304_amd as zinc
 from gpu_util import empty_u64, from_dev, gpu_ctx, ids, oracle_keys, to_dev, torch_cuda
-from paper_2408_07304_amd.workloads import PARAM_SETS, W_LARGE, W_MAIN, W_MIXED, W_SMALL, make_slots
+from paper_2408_07304_amd.workloads import (PARAM_SETS, TABLE2, W_LARGE, W_MAIN, W_MIXED, W_SMALL, dataset_rows,
+                                            make_slots)
 
 pytestmark = pytest.mark.gpu
 
-NAMES = ["n4096", "n8192", "n16384", "n32768"]
+NAMES = ["n4096", "n8192", "n16384", "n32768", "n32768_q16"]
 SCHEMES = [zinc.ZINC_SCHEME_VANILLA, zinc.ZINC_SCHEME_ZINC]
 
 
@@ -146,7 +147,7 @@ def test_encrypt_from_plaintext_bit_exact(name, scheme):
 def test_encode_within_tie_window(name):
     c = gpu_ctx(name)
     P = oracle_keys(name)[0]
-    w = {"n4096": W_SMALL, "n8192": W_MAIN, "n16384": W_LARGE, "n32768": W_MIXED}[name]
+    w = {"n4096": W_SMALL, "n8192": W_MAIN, "n16384": W_LARGE, "n32768": W_MIXED, "n32768_q16": W_MIXED}[name]
     z = make_slots(w, 3, PARAM_SETS[name])
     z[2, 100:] = 0.0                                     # also a partly empty vector
     out = empty_u64(3, P.L, P.n)
@@ -363,3 +364,34 @@ def test_full_batch_n16384_sampled(scheme):
 @pytest.mark.parametrize("scheme", SCHEMES)
 def test_full_batch_n4096(scheme):
     _check_fused_against_oracle("n4096", W_SMALL, list(range(0, 64, 9)), scheme)
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_table2_shapes_at_paper_parameters(scheme):
+    """The paper's parameters (N = 32768, 16 primes, Delta = 2^55) on rows of
+    the shapes of its evaluation datasets (16, 1 and 3 values per row, padded
+    with zeros to N/2 slots): sampled ciphertexts against the oracle as in the
+    full-batch tests."""
+    c = gpu_ctx("n32768_q16")
+    P, sh, pk, zero = oracle_keys("n32768_q16")
+    key = zero if scheme == zinc.ZINC_SCHEME_ZINC else pk
+    for d in TABLE2:
+        z = dataset_rows(d, 0, 3)
+        ct = empty_u64(3, 2, P.L, P.n)
+        first = 1000 * len(d.name)
+        say(f"table-2 shape {d.name} ({d.slots} values per row) scheme={scheme}")
+        c.encrypt_slots(scheme, to_dev(z), ids(range(first, first + 3)), ct)
+        got = from_dev(ct)
+        for i in range(3):
+            want = oracle.encrypt_slots(P, scheme, key, z[i], first + i)
+            assert np.array_equal(got[i][1], want[1]), (d.name, i)
+            if np.array_equal(got[i][0], want[0]):
+                continue
+            m, fr = oracle.encode(P, z[i])
+            tie = np.abs(np.abs(fr) - 0.5) <= tie_tau(P.n, np.abs(m).max())
+            for l, q in enumerate(P.data_moduli):
+                diff = ((got[i][0, l].astype(object) - want[0, l].astype(object)) % q).astype(np.uint64)
+                dd = to_dev(diff[None, :])
+                c.ntt_inverse(l, dd)
+                delta = centred(from_dev(dd)[0], q)
+                assert np.abs(delta).max() <= 1 and np.all(tie[delta != 0]), (d.name, i, l)

@@ -162,3 +162,18 @@ def test_mulmod_powmod(orc):
         assert orc.lib().oracle_mulmod(a, b, q) == (a * b) % q
         e = rng.getrandbits(64)
         assert orc.lib().oracle_powmod(a, e, q) == pow(a, e, q)
+
+
+def test_paper_chain_is_881_bits(orc):
+    """The paper's coefficient modulus (System Implementation section): 16
+    primes near 2^55, the last near 2^56, 881 bits in all (the standard's
+    maximum at N = 32768); each prime is = 1 mod 2N and they are distinct."""
+    from paper_2408_07304_amd.workloads import P32768_Q16
+    qs = orc.choose_moduli(P32768_Q16.log_n, P32768_Q16.bits)
+    assert len(set(qs)) == 16
+    Q = 1
+    for q in qs:
+        assert q % (2 * P32768_Q16.n) == 1 and orc.is_prime(q)
+        Q *= q
+    assert Q.bit_length() == 881
+    assert [q.bit_length() for q in qs] == [55] * 15 + [56]

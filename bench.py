@@ -130,6 +130,111 @@ def cpu_baseline(ws, scheme: int, budget_s: float):
                       f"{'Zinc' if scheme == 1 else 'vanilla'} encrypt), {threads} threads, {dt:.1f} s"}
 
 
+_ORACLE_KEYS = {}
+
+
+def _oracle_key(ps, scheme: int):
+    import oracle
+
+    if ps.name not in _ORACLE_KEYS:
+        P = oracle.Params(ps.log_n, ps.bits, ps.scale, ps.seed)
+        _, pk = oracle.keygen(P)
+        _ORACLE_KEYS[ps.name] = (P, pk, oracle.zinc_precompute(P, pk))
+    P, pk, zero = _ORACLE_KEYS[ps.name]
+    return P, (zero if scheme == 1 else pk)
+
+
+def oracle_rate(items, scheme: int, threads: int, budget_s: float) -> dict:
+    """Oracle encode + encrypt throughput over a bounded prefix of `items`
+    ((ParamSet, slot vector) pairs), `threads` plaintexts at a time."""
+    import concurrent.futures as cf
+
+    import oracle
+
+    keys = {}
+    for ps, _ in items:
+        if ps.name not in keys:
+            keys[ps.name] = _oracle_key(ps, scheme)
+    t0 = time.perf_counter()
+    P, key = keys[items[0][0].name]
+    oracle.encrypt_slots(P, scheme, key, items[0][1], 0)
+    one = time.perf_counter() - t0
+    count = int(min(len(items), max(threads, threads * budget_s / max(one, 1e-6))))
+
+    def enc(i):
+        P, key = keys[items[i][0].name]
+        return oracle.encrypt_slots(P, scheme, key, items[i][1], i)
+
+    t0 = time.perf_counter()
+    if threads == 1:
+        for i in range(count):
+            enc(i)
+    else:
+        with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+            list(ex.map(enc, range(count)))
+    dt = time.perf_counter() - t0
+    return {"enc_per_s": count / dt, "plaintexts": count, "threads": threads, "seconds": dt}
+
+
+def bench_config_table(steps: int, warmup: int, budget_s: float) -> list:
+    """Every benchmark configuration (N = 4096, 8192, 16384 batches and the
+    mixed batch), both schemes: GPU enc/s (autotuned fused launch, or the
+    mixed plan) beside the oracle on one thread and on all host threads (up
+    to 16), each timed on a bounded prefix of the same plaintexts."""
+    import torch
+
+    import paper_2408_07304_amd as zinc
+    from paper_2408_07304_amd.workloads import W_LARGE, W_MAIN, W_MIXED, W_SMALL, make_mixed, make_slots
+
+    threads = max(1, min(os.cpu_count() or 1, 16))
+    rows = []
+    for ws in (W_SMALL, W_MAIN, W_LARGE):
+        ps = ws.params[0]
+        ctx = zinc.context_for(ps)
+        ctx.keygen()
+        ctx.precompute()
+        ctx.autotune(batch=ws.batch, cache_path=TUNE_CACHE)
+        zh = make_slots(ws)
+        z = torch.from_numpy(zh).to("cuda")
+        ids = torch.arange(ws.batch, dtype=torch.int64, device="cuda")
+        ct = torch.empty((ws.batch, 2, ps.limbs, ps.n), dtype=torch.int64, device="cuda")
+        items = [(ps, zh[i]) for i in range(ws.batch)]
+        for name, sch in (("zinc", 1), ("vanilla", 0)):
+            for _ in range(max(1, warmup)):
+                ctx.encrypt_slots(sch, z, ids, ct)
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(steps):
+                ctx.encrypt_slots(sch, z, ids, ct)
+            b.record()
+            torch.cuda.synchronize()
+            gpu = ws.batch / (a.elapsed_time(b) / steps / 1e3)
+            row = {"workload": ws.name, "scheme": name, "gpu_enc_per_s": gpu,
+                   "oracle_1_thread": oracle_rate(items, sch, 1, budget_s),
+                   "oracle_all_threads": oracle_rate(items, sch, threads, budget_s)}
+            rows.append(row)
+            print(f"[bench] config table: {row}", file=sys.stderr, flush=True)
+        del z, ct, ids
+        ctx.close()
+        torch.cuda.empty_cache()
+    mb = make_mixed(W_MIXED)
+    items = [(W_MIXED.params[int(mb.ctx_idx[i])],
+              mb.slots[int(mb.slot_off[i]): int(mb.slot_off[i]) + W_MIXED.params[int(mb.ctx_idx[i])].slots])
+             for i in range(len(mb.ct_id))]
+    mctx = mixed_contexts()
+    mixed = bench_mixed(mctx, steps, warmup)
+    for c in mctx:
+        c.close()
+    for name, sch in (("zinc", 1), ("vanilla", 0)):
+        row = {"workload": W_MIXED.name, "scheme": name, "gpu_enc_per_s": mixed[f"{name}_enc_per_s"],
+               "oracle_1_thread": oracle_rate(items, sch, 1, budget_s),
+               "oracle_all_threads": oracle_rate(items, sch, threads, budget_s)}
+        rows.append(row)
+        print(f"[bench] config table: {row}", file=sys.stderr, flush=True)
+    return rows
+
+
 def bench_elementwise(ctx, ps, batch: int, steps: int, warmup: int) -> dict:
     """The element-wise steps alone (Algorithm 1's additions, Eq. 8's products
     and additions) on `batch` ciphertexts of transform outputs: HBM-bound
@@ -317,6 +422,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--scheme", choices=["both", "zinc", "vanilla"], default="both")
     ap.add_argument("--no-tune", action="store_true", help="keep the default kernel configuration")
+    ap.add_argument("--config-table", action="store_true",
+                    help="also measure every configuration, both schemes, GPU and oracle (1 and all threads)")
     ap.add_argument("--no-table2", action="store_true",
                     help="skip the paper-parameter runs on rows shaped like its datasets")
     ap.add_argument("--tune-cache", default=TUNE_CACHE,
@@ -451,6 +558,8 @@ def main():
             c.close()
     if not args.no_table2:
         line["table2_shapes"] = bench_table2()
+    if args.config_table:
+        line["config_table"] = bench_config_table(args.steps, args.warmup, args.cpu_budget / 4)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(ws, sch, args.cpu_budget)
     print(json.dumps(line), flush=True)

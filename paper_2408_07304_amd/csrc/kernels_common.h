@@ -159,8 +159,15 @@ struct MessageIn {
     }
     __device__ __forceinline__ double rf(int c) const {    // |value| <= q
         const uint32_t k = tp0 | G::cpart(0, c);
-        if constexpr (FROM_SLOTS) return u64_to_fp(reduce_signed(stash[k] + e.get(c), lc));
-        else return u64_to_fp(pt[k]) + (double)e.get(c);
+        if constexpr (FROM_SLOTS) {
+            // below 2^52 the integer converts exactly and one rounded quotient
+            // brings it into [-q, q]; larger messages take the integer route
+            const long long x = stash[k] + e.get(c);
+            if (x > -(1ll << 52) && x < (1ll << 52)) return fp_round_reduce((double)x, lc.qd, lc.qinv);
+            return u64_to_fp(reduce_signed(x, lc));
+        } else {
+            return u64_to_fp(pt[k]) + (double)e.get(c);
+        }
     }
 };
 

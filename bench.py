@@ -420,7 +420,8 @@ def main():
     ap.add_argument("--workload", default="n8192_b1024")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--scheme", choices=["both", "zinc", "vanilla"], default="both")
+    ap.add_argument("--scheme", choices=["both", "zinc", "vanilla", "vanilla_sp"], default="both",
+                    help="'both' runs Zinc, vanilla and the special-prime vanilla")
     ap.add_argument("--no-tune", action="store_true", help="keep the default kernel configuration")
     ap.add_argument("--config-table", action="store_true",
                     help="also measure every configuration, both schemes, GPU and oracle (1 and all threads)")
@@ -470,8 +471,8 @@ def main():
     ct = torch.empty((ws.batch, 2, ps.limbs, ps.n), dtype=torch.int64, device=dev)
     torch.cuda.synchronize()
 
-    schemes = {"zinc": 1, "vanilla": 0}
-    run = [s for s in ("zinc", "vanilla") if args.scheme in ("both", s)]
+    schemes = {"zinc": 1, "vanilla": 0, "vanilla_sp": 2}
+    run = [s for s in ("zinc", "vanilla", "vanilla_sp") if args.scheme in ("both", s)]
     res = {}
     for name in run:
         sch = schemes[name]
@@ -544,6 +545,10 @@ def main():
         line[f"{name}_kernel_ms"] = res[name]["kernel_ms"]
     if "vanilla" in res and "zinc" in res:
         line["zinc_over_vanilla"] = res["vanilla"]["ms_per_step"] / res["zinc"]["ms_per_step"]
+    if "vanilla_sp" in res and "zinc" in res:
+        # vanilla as a library with a special prime computes it (division by
+        # the prime with rounding), the form of the paper's CPU baseline
+        line["zinc_over_vanilla_sp"] = res["vanilla_sp"]["ms_per_step"] / res["zinc"]["ms_per_step"]
     line["elementwise"] = bench_elementwise(ctx, ps, ws.batch, args.steps, args.warmup)
     if not args.no_mixed:
         del ct, z

@@ -71,8 +71,9 @@ typedef int zinc_status;
 #define ZINC_ZERO_ID 0xFFFFFFFFFFFFFFFEull
 #define ZINC_MAX_MODULI 32
 
-#define ZINC_SCHEME_VANILLA 0
-#define ZINC_SCHEME_ZINC    1
+#define ZINC_SCHEME_VANILLA    0
+#define ZINC_SCHEME_ZINC       1
+#define ZINC_SCHEME_VANILLA_SP 2   /* zinc_encrypt_slots only: see zinc_encrypt_vanilla_sp */
 
 /* Message describing the calling thread's last failed call ("" if none). */
 const char* zinc_last_error(void);
@@ -166,9 +167,10 @@ zinc_status zinc_encrypt_vanilla(zinc_ctx* ctx, const uint64_t* d_pt, uint32_t b
 zinc_status zinc_encrypt(zinc_ctx* ctx, const uint64_t* d_pt, uint32_t batch,
                          const uint64_t* d_ct_ids, uint64_t* d_ct, void* stream);
 
-/* Encode and encrypt in one fused launch (scheme = ZINC_SCHEME_VANILLA or
- * ZINC_SCHEME_ZINC): the result is bit-identical to zinc_encode followed by
- * zinc_encrypt_vanilla / zinc_encrypt.  d_slots [batch][n_slots]. */
+/* Encode and encrypt in one fused launch (scheme = ZINC_SCHEME_VANILLA,
+ * ZINC_SCHEME_ZINC or ZINC_SCHEME_VANILLA_SP): the result is bit-identical to
+ * zinc_encode followed by zinc_encrypt_vanilla / zinc_encrypt /
+ * zinc_encrypt_vanilla_sp.  d_slots [batch][n_slots]. */
 zinc_status zinc_encrypt_slots(zinc_ctx* ctx, int scheme, const double* d_slots, uint32_t n_slots,
                                uint32_t batch, const uint64_t* d_ct_ids, uint64_t* d_ct,
                                void* stream);
@@ -183,6 +185,19 @@ zinc_status zinc_decrypt(zinc_ctx* ctx, const uint64_t* d_ct, uint32_t batch, ui
  * z_j = Re m(zeta^(5^j)) / Delta.  d_pt [batch][L][N] -> d_slots [batch][N/2]. */
 zinc_status zinc_decode(zinc_ctx* ctx, const uint64_t* d_pt, uint32_t batch, double* d_slots,
                         void* stream);
+
+/* Vanilla encryption the way a library with a special prime computes it (the
+ * paper's CPU baseline, SEAL, ends its chain in such a prime p, the context's
+ * last modulus): Eq. 8's encryption of zero over all M moduli,
+ * a_j = pk_j u + e_j, divided by p with rounding (coefficient-wise
+ * round(a_j / p), which leaves the L data limbs), then the message added to
+ * c1.  Same layouts as zinc_encrypt_vanilla; costlier (the special limb's
+ * transforms and two inverse transforms); N <= 16384 (ZINC_E_PARAM for
+ * 32768).  zinc_encrypt_slots with ZINC_SCHEME_VANILLA_SP is the fused form.
+ * Scratch of batch * 3 * N * 8 bytes is allocated and freed in `stream`'s
+ * order (hipMallocAsync). */
+zinc_status zinc_encrypt_vanilla_sp(zinc_ctx* ctx, const uint64_t* d_pt, uint32_t batch,
+                                    const uint64_t* d_ct_ids, uint64_t* d_ct, void* stream);
 
 /* The element-wise step of Zinc encryption alone (Algorithm 1's additions, in
  * the NTT domain where the cached Enc(0) is kept), for callers that compute

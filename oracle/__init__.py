@@ -86,6 +86,7 @@ def lib():
             "oracle_decrypt": (None, [P, _u64p, _u64p, _u64p]),
             "oracle_add": (None, [P, _u64p, _u64p, _u64p]),
             "oracle_elementwise_zinc": (None, [P, _u64p, _u64p, _u64p]),
+            "oracle_encrypt_vanilla_sp": (None, [P, _u64p, _u64p, ctypes.c_uint64, _u64p]),
             "oracle_elementwise_vanilla": (None, [P, _u64p, _u64p, _u64p, _u64p]),
             "oracle_encode": (None, [P, _f64p, ctypes.c_uint32, _i64p, _f64p]),
             "oracle_decode": (None, [P, _i64p, _f64p]),
@@ -247,6 +248,16 @@ def encrypt_vanilla(P: Params, pk, pt, ct_id: int) -> np.ndarray:
     return ct
 
 
+def encrypt_vanilla_sp(P: Params, pk, pt, ct_id: int) -> np.ndarray:
+    """Eq. 8 over the whole chain, then division by the special prime with
+    rounding down to the L data limbs, then + m (a SEAL-style vanilla)."""
+    pk = np.ascontiguousarray(pk, dtype=np.uint64)
+    pt = np.ascontiguousarray(pt, dtype=np.uint64)
+    ct = np.zeros((2, P.L, P.n), dtype=np.uint64)
+    lib().oracle_encrypt_vanilla_sp(P.ref(), _p(pk, _u64p), _p(pt, _u64p), ct_id, _p(ct, _u64p))
+    return ct
+
+
 def zinc_precompute(P: Params, pk) -> np.ndarray:
     """Zinc precomputation: cache one Enc(0) (vanilla, identifier ZERO_ID)."""
     pk = np.ascontiguousarray(pk, dtype=np.uint64)
@@ -330,7 +341,8 @@ def to_rns(P: Params, m, n_limbs: int | None = None) -> np.ndarray:
 
 def encrypt_slots(P: Params, scheme: int, key, z, ct_id: int) -> np.ndarray:
     """Encode then encrypt one slot vector; scheme 0 = vanilla (key = pk),
-    1 = Zinc (key = cached zero)."""
+    1 = Zinc (key = cached zero), 2 = vanilla with division by the special
+    prime (key = pk)."""
     key = np.ascontiguousarray(key, dtype=np.uint64)
     z = np.ascontiguousarray(z, dtype=np.float64)
     ct = np.zeros((2, P.L, P.n), dtype=np.uint64)

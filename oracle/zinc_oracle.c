@@ -342,6 +342,69 @@ void oracle_encrypt_vanilla(const oracle_params* p, const uint64_t* pk, const ui
     free(u); free(e1); free(e2); free(uh);
 }
 
+/* Vanilla encryption as a library with a special prime computes it (the
+ * paper's CPU baseline is SEAL, whose chain ends in such a prime p = q_{M-1};
+ * Eq. 8 read over the whole chain): the public-key encryption of zero over all
+ * M limbs, a_j = pk_j u + e_j (j = 1, 2), is divided by p with rounding,
+ * a_j' = round(a_j / p) coefficient-wise, which leaves the L data limbs, and
+ * then the message is added: c1 = a1' + m, c2 = a2'.  Rounding in RNS: with
+ * r = a_j mod p (coefficients in [0, p)), h = (p - 1) / 2 and
+ * t = (r + h) mod p, round(a_j / p) = (a_j + h - t) / p, an exact division,
+ * so limb l gets (a_j + (h - t)) p^-1 mod q_l.
+ * pk [2][M][N]; pt [L][N] coefficient domain; ct [2][L][N] NTT domain. */
+void oracle_encrypt_vanilla_sp(const oracle_params* p, const uint64_t* pk, const uint64_t* pt,
+                               uint64_t ct_id, uint64_t* ct) {
+    uint32_t n = 1u << p->log_n, M = p->n_moduli, L = M - 1;
+    uint64_t qp = p->q[L], h = (qp - 1) / 2;
+    int64_t* u = (int64_t*)malloc(sizeof(int64_t) * n);
+    int64_t* e[2];
+    e[0] = (int64_t*)malloc(sizeof(int64_t) * n);
+    e[1] = (int64_t*)malloc(sizeof(int64_t) * n);
+    uint64_t* a = (uint64_t*)malloc(sizeof(uint64_t) * 2 * (size_t)M * n);   /* [2][M][N] */
+    uint64_t* tmp = (uint64_t*)malloc(sizeof(uint64_t) * n);
+    int64_t* d = (int64_t*)malloc(sizeof(int64_t) * n);
+    oracle_sample_ternary(p->seed, ct_id, TAG_U, n, u);
+    oracle_sample_gaussian(p->seed, ct_id, TAG_E1, n, p->cdt, e[0]);
+    oracle_sample_gaussian(p->seed, ct_id, TAG_E2, n, p->cdt, e[1]);
+    /* encryption of zero over the whole chain, NTT domain */
+    for (uint32_t l = 0; l < M; l++) {
+        uint64_t q = p->q[l];
+        uint64_t* uh = tmp;
+        for (uint32_t k = 0; k < n; k++) uh[k] = smod(u[k], q);
+        oracle_ntt_forward(uh, p->log_n, q, p->psi[l]);
+        for (int j = 0; j < 2; j++) {
+            uint64_t* aj = a + ((size_t)j * M + l) * n;
+            const uint64_t* pkj = pk + ((size_t)j * M + l) * n;
+            for (uint32_t k = 0; k < n; k++) aj[k] = smod(e[j][k], q);
+            oracle_ntt_forward(aj, p->log_n, q, p->psi[l]);
+            for (uint32_t k = 0; k < n; k++) aj[k] = addmod(mulmod(pkj[k], uh[k], q), aj[k], q);
+        }
+    }
+    /* division by p with rounding, then the message */
+    for (int j = 0; j < 2; j++) {
+        memcpy(tmp, a + ((size_t)j * M + L) * n, sizeof(uint64_t) * n);
+        oracle_ntt_inverse(tmp, p->log_n, qp, p->psi[L]);                  /* r = a_j mod p */
+        for (uint32_t k = 0; k < n; k++) {
+            uint64_t t = addmod(tmp[k], h, qp);
+            d[k] = (int64_t)h - (int64_t)t;                                   /* h - t */
+        }
+        for (uint32_t l = 0; l < L; l++) {
+            uint64_t q = p->q[l], pinv = powmod(qp % q, q - 2, q);
+            for (uint32_t k = 0; k < n; k++) tmp[k] = smod(d[k], q);
+            oracle_ntt_forward(tmp, p->log_n, q, p->psi[l]);
+            uint64_t* out = ct + ((size_t)j * L + l) * n;
+            const uint64_t* aj = a + ((size_t)j * M + l) * n;
+            for (uint32_t k = 0; k < n; k++) out[k] = mulmod(addmod(aj[k], tmp[k], q), pinv, q);
+            if (j == 0) {
+                memcpy(tmp, pt + (size_t)l * n, sizeof(uint64_t) * n);
+                oracle_ntt_forward(tmp, p->log_n, q, p->psi[l]);
+                for (uint32_t k = 0; k < n; k++) out[k] = addmod(out[k], tmp[k], q);
+            }
+        }
+    }
+    free(u); free(e[0]); free(e[1]); free(a); free(tmp); free(d);
+}
+
 /* Zinc precomputation: the cached Enc(0) is a vanilla encryption of the zero
  * plaintext under the reserved identifier ZERO_ID. */
 void oracle_zinc_precompute(const oracle_params* p, const uint64_t* pk, uint64_t* zero) {
@@ -508,6 +571,7 @@ void oracle_encrypt_slots(const oracle_params* p, int scheme, const uint64_t* pk
     oracle_encode(p, z, n_slots, m, NULL);
     oracle_to_rns(p, m, L, pt);
     if (scheme == 0) oracle_encrypt_vanilla(p, pk_or_zero, pt, ct_id, ct);
+    else if (scheme == 2) oracle_encrypt_vanilla_sp(p, pk_or_zero, pt, ct_id, ct);
     else oracle_encrypt_zinc(p, pk_or_zero, pt, ct_id, ct);
     free(m); free(pt);
 }

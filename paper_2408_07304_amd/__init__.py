@@ -19,7 +19,7 @@ ZINC_E_INVAL, ZINC_E_PARAM, ZINC_E_STATE, ZINC_E_NOMEM, ZINC_E_HIP, ZINC_E_RANGE
 ZINC_KEY_ID = (1 << 64) - 1
 ZINC_ZERO_ID = (1 << 64) - 2
 ZINC_MAX_MODULI = 32
-ZINC_SCHEME_VANILLA, ZINC_SCHEME_ZINC = 0, 1
+ZINC_SCHEME_VANILLA, ZINC_SCHEME_ZINC, ZINC_SCHEME_VANILLA_SP = 0, 1, 2
 SAMPLE_TERNARY, SAMPLE_GAUSSIAN, SAMPLE_UNIFORM = 0, 1, 2
 
 _STATUS_NAMES = {-1: "ZINC_E_INVAL", -2: "ZINC_E_PARAM", -3: "ZINC_E_STATE", -4: "ZINC_E_NOMEM",
@@ -96,6 +96,7 @@ _SIGS = {
     "zinc_encode": (ctypes.c_int, [_vp, _vp, _u32, _u32, _vp, _vp]),
     "zinc_encrypt_vanilla": (ctypes.c_int, [_vp, _vp, _u32, _vp, _vp, _vp]),
     "zinc_encrypt": (ctypes.c_int, [_vp, _vp, _u32, _vp, _vp, _vp]),
+    "zinc_encrypt_vanilla_sp": (ctypes.c_int, [_vp, _vp, _u32, _vp, _vp, _vp]),
     "zinc_encrypt_slots": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _u32, _u32, _vp, _vp, _vp]),
     "zinc_decrypt": (ctypes.c_int, [_vp, _vp, _u32, _vp, _vp]),
     "zinc_decode": (ctypes.c_int, [_vp, _vp, _u32, _vp, _vp]),
@@ -271,6 +272,12 @@ class Context:
     def encrypt_vanilla(self, pt, ct_ids, out, stream=None):
         _check(load_library().zinc_encrypt_vanilla(self.handle, _ptr(pt), pt.shape[0], _ptr(ct_ids), _ptr(out),
                                                    _stream(stream)))
+        return out
+
+    def encrypt_vanilla_sp(self, pt, ct_ids, out, stream=None):
+        """Vanilla with division by the special prime (a SEAL-style baseline)."""
+        _check(load_library().zinc_encrypt_vanilla_sp(self.handle, _ptr(pt), pt.shape[0], _ptr(ct_ids), _ptr(out),
+                                                      _stream(stream)))
         return out
 
     def encrypt(self, pt, ct_ids, out, stream=None):

@@ -110,6 +110,10 @@ zinc_status zinc_ctx_create(const zinc_params* p, zinc_ctx** out) {
         limbs[l].ninv = powmod_host(n, ql - 2, ql);
         limbs[l].ninv_sh = shoup_companion(limbs[l].ninv, ql);
         limbs[l].half = (ql - 1) / 2;
+        if (l + 1 < M) {
+            limbs[l].pinv = powmod_host(q[M - 1] % ql, ql - 2, ql);
+            limbs[l].pinv_sh = shoup_companion(limbs[l].pinv, ql);
+        }
         limbs[l].qd = (double)ql;
         limbs[l].qinv = (double)(1.0L / (long double)ql);
         limbs[l].fp = force_int || ql >= kFpBound ? 0u : (ql >= kFpNoReduceBound ? 2u : 1u);
@@ -163,7 +167,8 @@ zinc_status zinc_ctx_create(const zinc_params* p, zinc_ctx** out) {
     const size_t o_pos = take(4 * H), o_cdt = take(8 * kCdtTab);
     const size_t o_sk = take(nb * M), o_sks = take(nb * M);
     const size_t o_pk = take(nb * 2 * M), o_pks = take(nb * 2 * M);
-    const size_t o_zero = take(nb * 2 * L), o_err = take(256);
+    const size_t o_zero = take(nb * 2 * L), o_pkp = take(nb * 2 * L), o_pkps = take(nb * 2 * L);
+    const size_t o_err = take(256);
     char* base = nullptr;
     hipError_t e = hipMalloc(&base, off);
     if (e != hipSuccess) {
@@ -211,6 +216,8 @@ zinc_status zinc_ctx_create(const zinc_params* p, zinc_ctx** out) {
     d.pk = reinterpret_cast<const uint64_t*>(base + o_pk);
     d.pk_sh = reinterpret_cast<const uint64_t*>(base + o_pks);
     d.zero = reinterpret_cast<const uint64_t*>(base + o_zero);
+    d.pkp = reinterpret_cast<const uint64_t*>(base + o_pkp);
+    d.pkp_sh = reinterpret_cast<const uint64_t*>(base + o_pkps);
     d.err = reinterpret_cast<uint32_t*>(base + o_err);
     *out = c;
     return ZINC_OK;
@@ -261,6 +268,10 @@ zinc_status zinc_keygen(zinc_ctx* c, void* stream) {
                                             const_cast<uint64_t*>(d.pk), const_cast<uint64_t*>(d.pk_sh),
                                             (hipStream_t)stream),
                               "keygen launch");
+    if (st == ZINC_OK)
+        st = launched(launch_scale_pk(d, const_cast<uint64_t*>(d.pkp), const_cast<uint64_t*>(d.pkp_sh),
+                                      (hipStream_t)stream),
+                      "keygen launch");
     if (st == ZINC_OK) {
         c->keyed = true;
         c->precomputed = false;
@@ -297,6 +308,22 @@ static zinc_status check_batch(const char* fn, uint32_t batch, std::initializer_
     return ZINC_OK;
 }
 
+// Special-prime vanilla: scratch of [batch][3][N] int64 (message and the two
+// rounding offsets), allocated and freed in stream order around the launch.
+static zinc_status encrypt_sp(zinc_ctx* c, bool from_slots, const double* slots, uint32_t n_slots,
+                              const uint64_t* pt, uint32_t batch, const uint64_t* ids, uint64_t* ct, void* stream) {
+    if (c->log_n == 15) return fail(ZINC_E_PARAM, "special-prime vanilla is built for N <= 16384");
+    hipStream_t s = (hipStream_t)stream;
+    int64_t* ws = nullptr;
+    hipError_t e = hipMallocAsync((void**)&ws, (size_t)batch * 3 * c->n * sizeof(int64_t), s);
+    if (e != hipSuccess) return fail(ZINC_E_NOMEM, "special-prime vanilla: scratch allocation failed");
+    const hipError_t le = launch_encrypt_sp(c->dev, from_slots, slots, n_slots, pt, batch, ids, ct, ws, s);
+    e = hipFreeAsync(ws, s);
+    if (le != hipSuccess) return hip_fail(le, "special-prime vanilla launch");
+    if (e != hipSuccess) return hip_fail(e, "special-prime vanilla: scratch release");
+    return ZINC_OK;
+}
+
 zinc_status zinc_encode(zinc_ctx* c, const double* slots, uint32_t n_slots, uint32_t batch, uint64_t* pt,
                         void* stream) {
     if (!c) return fail(ZINC_E_INVAL, "zinc_encode: null context");
@@ -329,14 +356,15 @@ zinc_status zinc_encrypt(zinc_ctx* c, const uint64_t* pt, uint32_t batch, const 
 zinc_status zinc_encrypt_slots(zinc_ctx* c, int scheme, const double* slots, uint32_t n_slots, uint32_t batch,
                                const uint64_t* ids, uint64_t* ct, void* stream) {
     if (!c) return fail(ZINC_E_INVAL, "zinc_encrypt_slots: null context");
-    if (scheme != ZINC_SCHEME_VANILLA && scheme != ZINC_SCHEME_ZINC)
-        return fail(ZINC_E_INVAL, "zinc_encrypt_slots: scheme must be 0 (vanilla) or 1 (zinc)");
+    if (scheme != ZINC_SCHEME_VANILLA && scheme != ZINC_SCHEME_ZINC && scheme != ZINC_SCHEME_VANILLA_SP)
+        return fail(ZINC_E_INVAL, "zinc_encrypt_slots: scheme must be 0 (vanilla), 1 (zinc) or 2 (vanilla_sp)");
     if (!c->keyed) return fail(ZINC_E_STATE, "zinc_encrypt_slots before zinc_keygen");
     if (scheme == ZINC_SCHEME_ZINC && !c->precomputed)
         return fail(ZINC_E_STATE, "zinc_encrypt_slots (zinc) before zinc_precompute");
     if (n_slots > c->n / 2) return fail(ZINC_E_RANGE, "zinc_encrypt_slots: n_slots exceeds N/2");
     if (zinc_status s = check_batch("zinc_encrypt_slots", batch, {slots, ids, ct})) return s;
     if (batch == 0) return ZINC_OK;
+    if (scheme == ZINC_SCHEME_VANILLA_SP) return encrypt_sp(c, true, slots, n_slots, nullptr, batch, ids, ct, stream);
     const uint32_t tile = c->tile[scheme];
     const bool reg = (c->reg_epilogue >> scheme) & 1u;
     if (tile != 16 || reg)
@@ -345,6 +373,15 @@ zinc_status zinc_encrypt_slots(zinc_ctx* c, int scheme, const double* slots, uin
                         "fused encrypt launch");
     return launched(launch_encrypt_slots(c->dev, scheme, slots, n_slots, batch, ids, ct, (hipStream_t)stream),
                     "fused encrypt launch");
+}
+
+zinc_status zinc_encrypt_vanilla_sp(zinc_ctx* c, const uint64_t* pt, uint32_t batch, const uint64_t* ids,
+                                    uint64_t* ct, void* stream) {
+    if (!c) return fail(ZINC_E_INVAL, "zinc_encrypt_vanilla_sp: null context");
+    if (!c->keyed) return fail(ZINC_E_STATE, "zinc_encrypt_vanilla_sp before zinc_keygen");
+    if (zinc_status s = check_batch("zinc_encrypt_vanilla_sp", batch, {pt, ids, ct})) return s;
+    if (batch == 0) return ZINC_OK;
+    return encrypt_sp(c, false, nullptr, 0, pt, batch, ids, ct, stream);
 }
 
 zinc_status zinc_elementwise_zinc(zinc_ctx* c, const uint64_t* hat, uint32_t batch, uint64_t* ct, void* stream) {

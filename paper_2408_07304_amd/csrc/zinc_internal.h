@@ -28,6 +28,8 @@ struct LimbConst {
     uint64_t ninv;      // N^-1 mod q
     uint64_t ninv_sh;   // Shoup companion of N^-1
     uint64_t half;      // (q - 1) / 2, centred-lift threshold
+    uint64_t pinv;      // p^-1 mod q for the special prime p = q_{M-1} (data limbs)
+    uint64_t pinv_sh;   // Shoup companion of pinv
     double qd;          // q as a double (exact)
     double qinv;        // 1/q rounded to double
     uint32_t fp;        // forward-NTT arithmetic: 0 integer (Shoup), 1 FP64, 2 FP64 with per-pass rounding
@@ -56,6 +58,8 @@ struct DevParams {
     const uint64_t* pk;           // [2][M][N]
     const uint64_t* pk_sh;        // [2][M][N]
     const uint64_t* zero;         // [2][L][N]  cached Enc(0)
+    const uint64_t* pkp;          // [2][L][N]  pk_j p^-1 on the data limbs (special-prime vanilla)
+    const uint64_t* pkp_sh;       // [2][L][N]  Shoup companions
     uint32_t* err;                // sticky device error flags
 };
 
@@ -141,6 +145,13 @@ hipError_t launch_ntt(const DevParams& p, bool inverse, uint32_t limb, uint64_t*
                       uint32_t n_polys, hipStream_t s);
 hipError_t launch_sample(const DevParams& p, int kind, uint32_t tag, uint32_t limb,
                          const uint64_t* ct_ids, uint32_t batch, void* out, hipStream_t s);
+
+// vanilla with division by the special prime (kernels_sp.hip); ws holds
+// [batch][3][N] int64 of scratch
+hipError_t launch_scale_pk(const DevParams& p, uint64_t* pkp, uint64_t* pkp_sh, hipStream_t s);
+hipError_t launch_encrypt_sp(const DevParams& p, bool from_slots, const double* slots, uint32_t n_slots,
+                             const uint64_t* pt, uint32_t batch, const uint64_t* ct_ids, uint64_t* ct, int64_t* ws,
+                             hipStream_t s);
 
 // element-wise steps alone (kernels_elementwise.hip)
 hipError_t launch_elementwise_zinc(const DevParams& p, const uint64_t* hat, uint32_t batch, uint64_t* ct,

@@ -231,3 +231,48 @@ def test_elementwise_vanilla_products_decrypt(orc, setup):
                      for l, q in enumerate(P.data_moduli)])
     ct = orc.elementwise_vanilla(P, pk, uhat, np.zeros((2, P.L, P.n), dtype=np.uint64))
     assert np.array_equal(orc.decrypt(P, sh, ct), residues(negacyclic(e, u), P.data_moduli))
+
+
+def test_vanilla_sp_is_rounded_division_by_the_special_prime(orc, setup):
+    """The special-prime vanilla equals, coefficient by coefficient, the exact
+    integer rounding floor((a + h) / p) of the chain-wide encryption of zero
+    a = pk u + e (lifted by Chinese remaindering over all M moduli,
+    h = (p - 1) / 2), reduced to each data limb, plus the message."""
+    P, sh, pk, zero, s, e = setup
+    ct_id = 5
+    m = _message(P, 3)
+    ct = orc.encrypt_vanilla_sp(P, pk, orc.to_rns(P, m), ct_id)
+    u = orc.sample_ternary(P.seed, ct_id, orc.TAG_U, P.n)
+    es = [orc.sample_gaussian(P.seed, ct_id, orc.TAG_E1, P.n), orc.sample_gaussian(P.seed, ct_id, orc.TAG_E2, P.n)]
+    qs = [int(q) for q in P.moduli]
+    M, L, p = len(qs), P.L, qs[-1]
+    big = 1
+    for q in qs:
+        big *= q
+    basis = [(big // q) * pow(big // q, -1, q) for q in qs]
+    h = (p - 1) // 2
+    for j in range(2):
+        rows = []
+        for l, q in enumerate(qs):
+            uh = orc.ntt_forward(residues(u, [q])[0], P.log_n, q, P.psi[l])
+            eh = orc.ntt_forward(residues(es[j], [q])[0], P.log_n, q, P.psi[l])
+            ah = [(int(pk[j, l, k]) * int(uh[k]) + int(eh[k])) % q for k in range(P.n)]
+            rows.append([int(x) for x in orc.ntt_inverse(ah, P.log_n, q, P.psi[l])])
+        x = [sum(rows[l][k] * basis[l] for l in range(M)) % big for k in range(P.n)]
+        y = [(xi + h) // p for xi in x]
+        for l in range(L):
+            q = qs[l]
+            got = [int(v) for v in orc.ntt_inverse(ct[j, l], P.log_n, q, P.psi[l])]
+            want = [(yk + (int(m[k]) if j == 0 else 0)) % q for k, yk in enumerate(y)]
+            assert got == want, (j, l)
+
+
+def test_vanilla_sp_decrypts_with_tiny_noise(orc, setup):
+    """Division by p shrinks the encryption noise e u + e1 + e2 s by p; what is
+    left is the rounding, at most about (1 + |s|_1) / 2 per coefficient."""
+    P, sh, pk, zero, s, e = setup
+    m = _message(P, 8)
+    ct = orc.encrypt_vanilla_sp(P, pk, orc.to_rns(P, m), 9)
+    dec = orc.crt_centered(P, orc.decrypt(P, sh, ct))
+    noise = np.array([d - int(x) for d, x in zip(dec, m)], dtype=np.int64)
+    assert np.abs(noise).max() <= (1 + int(np.abs(s).sum())) // 2 + 1

@@ -199,6 +199,23 @@ zinc_status zinc_decode(zinc_ctx* ctx, const uint64_t* d_pt, uint32_t batch, dou
 zinc_status zinc_encrypt_vanilla_sp(zinc_ctx* ctx, const uint64_t* d_pt, uint32_t batch,
                                     const uint64_t* d_ct_ids, uint64_t* d_ct, void* stream);
 
+/* BFV on the same contexts (Scheme Flexibility section, Eq. 12): the message
+ * is scaled by Delta = floor(Q / t), Q the product of the data moduli, and the
+ * rest of the encryption is unchanged, so zinc_encrypt (Zinc) and
+ * zinc_encrypt_vanilla (Eq. 8) encrypt BFV plaintexts as they are.
+ * Plaintexts: integer polynomials with coefficients in Z_t, one per ring
+ * coefficient (the BFV batch encoding is not provided), int64 [batch][N],
+ * any representative (reduced mod t by the encoding).
+ * zinc_bfv_encode: d_m -> d_pt [batch][L][N] = Delta * m mod q_l.
+ * zinc_bfv_decode: decrypted residues d_pt [batch][L][N] (zinc_decrypt) ->
+ * d_m = round(t x / Q) mod t, centred in (-t/2, t/2], x the residues'
+ * CRT value (RNS scale-and-round; correct while the noise is below Delta/2).
+ * t in [2, 2^32) and below every data modulus (ZINC_E_INVAL otherwise). */
+zinc_status zinc_bfv_encode(zinc_ctx* ctx, uint64_t t, const int64_t* d_m, uint32_t batch, uint64_t* d_pt,
+                            void* stream);
+zinc_status zinc_bfv_decode(zinc_ctx* ctx, uint64_t t, const uint64_t* d_pt, uint32_t batch, int64_t* d_m,
+                            void* stream);
+
 /* The element-wise step of Zinc encryption alone (Algorithm 1's additions, in
  * the NTT domain where the cached Enc(0) is kept), for callers that compute
  * the transforms themselves: d_ct = d_hat + Enc(0) component-wise mod q_l,

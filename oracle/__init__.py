@@ -351,6 +351,38 @@ def encrypt_slots(P: Params, scheme: int, key, z, ct_id: int) -> np.ndarray:
     return ct
 
 
+def bfv_delta(P: Params, t: int) -> int:
+    """BFV's scale Delta = floor(Q / t), Q the product of the data moduli
+    (Scheme Flexibility section, Eq. 12)."""
+    Q = 1
+    for q in P.data_moduli:
+        Q *= int(q)
+    return Q // t
+
+
+def bfv_encode(P: Params, t: int, m) -> np.ndarray:
+    """BFV plaintext scaling: residues of Delta * (m mod t) per data limb,
+    [L][N] (coefficient encoding: one element of Z_t per ring coefficient)."""
+    d = bfv_delta(P, t)
+    return np.array([[(d * (int(x) % t)) % int(q) for x in m] for q in P.data_moduli], dtype=np.uint64)
+
+
+def bfv_decode(P: Params, t: int, pt) -> np.ndarray:
+    """BFV decoding of decrypted residues [L][N]: x = CRT value in [0, Q),
+    m = round(t x / Q) mod t (halves rounded up), centred to (-t/2, t/2]."""
+    qs = [int(q) for q in P.data_moduli]
+    Q = 1
+    for q in qs:
+        Q *= q
+    basis = [(Q // q) * pow(Q // q, -1, q) for q in qs]
+    out = []
+    for k in range(P.n):
+        x = sum(int(pt[l][k]) * basis[l] for l in range(len(qs))) % Q
+        r = ((2 * t * x + Q) // (2 * Q)) % t
+        out.append(r - t if r > t // 2 else r)
+    return np.array(out, dtype=np.int64)
+
+
 def crt_centered(P: Params, pt, limbs: int | None = None) -> list[int]:
     """Exact centred lift of RNS residues [L][N] to integers in (-Q/2, Q/2]
     (Chinese remaindering with Python integers)."""

@@ -97,6 +97,8 @@ _SIGS = {
     "zinc_encrypt_vanilla": (ctypes.c_int, [_vp, _vp, _u32, _vp, _vp, _vp]),
     "zinc_encrypt": (ctypes.c_int, [_vp, _vp, _u32, _vp, _vp, _vp]),
     "zinc_encrypt_vanilla_sp": (ctypes.c_int, [_vp, _vp, _u32, _vp, _vp, _vp]),
+    "zinc_bfv_encode": (ctypes.c_int, [_vp, ctypes.c_uint64, _vp, _u32, _vp, _vp]),
+    "zinc_bfv_decode": (ctypes.c_int, [_vp, ctypes.c_uint64, _vp, _u32, _vp, _vp]),
     "zinc_encrypt_slots": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _u32, _u32, _vp, _vp, _vp]),
     "zinc_decrypt": (ctypes.c_int, [_vp, _vp, _u32, _vp, _vp]),
     "zinc_decode": (ctypes.c_int, [_vp, _vp, _u32, _vp, _vp]),
@@ -278,6 +280,16 @@ class Context:
         """Vanilla with division by the special prime (a SEAL-style baseline)."""
         _check(load_library().zinc_encrypt_vanilla_sp(self.handle, _ptr(pt), pt.shape[0], _ptr(ct_ids), _ptr(out),
                                                       _stream(stream)))
+        return out
+
+    def bfv_encode(self, t: int, m, out, stream=None):
+        """BFV plaintexts (int64 [batch][N] in Z_t) -> Delta * m residues."""
+        _check(load_library().zinc_bfv_encode(self.handle, int(t), _ptr(m), m.shape[0], _ptr(out), _stream(stream)))
+        return out
+
+    def bfv_decode(self, t: int, pt, out, stream=None):
+        """Decrypted residues -> BFV plaintexts (int64, centred mod t)."""
+        _check(load_library().zinc_bfv_decode(self.handle, int(t), _ptr(pt), pt.shape[0], _ptr(out), _stream(stream)))
         return out
 
     def encrypt(self, pt, ct_ids, out, stream=None):

@@ -384,6 +384,51 @@ zinc_status zinc_encrypt_vanilla_sp(zinc_ctx* c, const uint64_t* pt, uint32_t ba
     return encrypt_sp(c, false, nullptr, 0, pt, batch, ids, ct, stream);
 }
 
+// Constants of the BFV encoding / decoding for plaintext modulus t.
+static zinc_status bfv_consts(const zinc_ctx* c, uint64_t t, BfvConsts* k, const char* fn) {
+    if (t < 2 || t >= (1ull << 32)) return fail(ZINC_E_INVAL, std::string(fn) + ": t must be in [2, 2^32)");
+    const uint32_t L = c->L;
+    for (uint32_t l = 0; l < L; ++l)
+        if (t >= c->q[l]) return fail(ZINC_E_INVAL, std::string(fn) + ": t must be below every data modulus");
+    std::memset(k, 0, sizeof(*k));
+    k->t = t;
+    uint64_t q_mod_t = 1 % t;                                  // Q mod t
+    for (uint32_t l = 0; l < L; ++l) q_mod_t = (uint64_t)((unsigned __int128)q_mod_t * (c->q[l] % t) % t);
+    for (uint32_t l = 0; l < L; ++l) {
+        const uint64_t q = c->q[l];
+        uint64_t prod = 1;                                     // (Q / q_l) mod q_l
+        for (uint32_t j = 0; j < L; ++j)
+            if (j != l) prod = mulmod_host(prod, c->q[j] % q, q);
+        const uint64_t qt = powmod_host(prod, q - 2, q);        // Qt_l
+        const unsigned __int128 tq = (unsigned __int128)t * qt;
+        k->b[l] = (uint64_t)(tq % q);
+        k->b_sh[l] = shoup_companion(k->b[l], q);
+        k->w_mod_t[l] = (uint64_t)((tq / q) % t);
+        const uint64_t tinv = powmod_host(t % q, q - 2, q);
+        k->delta[l] = mulmod_host((q - q_mod_t % q) % q, tinv, q); // (Q - (Q mod t)) / t mod q_l
+        k->delta_sh[l] = shoup_companion(k->delta[l], q);
+    }
+    return ZINC_OK;
+}
+
+zinc_status zinc_bfv_encode(zinc_ctx* c, uint64_t t, const int64_t* m, uint32_t batch, uint64_t* pt, void* stream) {
+    if (!c) return fail(ZINC_E_INVAL, "zinc_bfv_encode: null context");
+    if (zinc_status s = check_batch("zinc_bfv_encode", batch, {m, pt})) return s;
+    BfvConsts k;
+    if (zinc_status s = bfv_consts(c, t, &k, "zinc_bfv_encode")) return s;
+    if (batch == 0) return ZINC_OK;
+    return launched(launch_bfv_encode(c->dev, k, m, batch, pt, (hipStream_t)stream), "BFV encode launch");
+}
+
+zinc_status zinc_bfv_decode(zinc_ctx* c, uint64_t t, const uint64_t* pt, uint32_t batch, int64_t* m, void* stream) {
+    if (!c) return fail(ZINC_E_INVAL, "zinc_bfv_decode: null context");
+    if (zinc_status s = check_batch("zinc_bfv_decode", batch, {pt, m})) return s;
+    BfvConsts k;
+    if (zinc_status s = bfv_consts(c, t, &k, "zinc_bfv_decode")) return s;
+    if (batch == 0) return ZINC_OK;
+    return launched(launch_bfv_decode(c->dev, k, pt, batch, m, (hipStream_t)stream), "BFV decode launch");
+}
+
 zinc_status zinc_elementwise_zinc(zinc_ctx* c, const uint64_t* hat, uint32_t batch, uint64_t* ct, void* stream) {
     if (!c) return fail(ZINC_E_INVAL, "zinc_elementwise_zinc: null context");
     if (!c->precomputed) return fail(ZINC_E_STATE, "zinc_elementwise_zinc before zinc_precompute");

@@ -63,6 +63,17 @@ struct DevParams {
     uint32_t* err;                // sticky device error flags
 };
 
+// Per-call constants of the BFV integer encoding and decoding for plaintext
+// modulus t (kernels_bfv.hip), one entry per data limb.
+struct BfvConsts {
+    uint64_t t;
+    uint64_t delta[ZINC_MAX_MODULI];      // floor(Q / t) mod q_l
+    uint64_t delta_sh[ZINC_MAX_MODULI];
+    uint64_t b[ZINC_MAX_MODULI];          // t Qt_l mod q_l, Qt_l = (Q / q_l)^-1 mod q_l
+    uint64_t b_sh[ZINC_MAX_MODULI];
+    uint64_t w_mod_t[ZINC_MAX_MODULI];    // floor(t Qt_l / q_l) mod t
+};
+
 // One ciphertext of a mixed-shape plan (device copy of a zinc_item).
 struct PlanItem {
     uint32_t ctx;            // index into the plan's contexts
@@ -151,6 +162,12 @@ hipError_t launch_sample(const DevParams& p, int kind, uint32_t tag, uint32_t li
 hipError_t launch_scale_pk(const DevParams& p, uint64_t* pkp, uint64_t* pkp_sh, hipStream_t s);
 hipError_t launch_encrypt_sp(const DevParams& p, bool from_slots, const double* slots, uint32_t n_slots,
                              const uint64_t* pt, uint32_t batch, const uint64_t* ct_ids, uint64_t* ct, int64_t* ws,
+                             hipStream_t s);
+
+// BFV integer encoding / decoding (kernels_bfv.hip)
+hipError_t launch_bfv_encode(const DevParams& p, const BfvConsts& k, const int64_t* m, uint32_t batch, uint64_t* pt,
+                             hipStream_t s);
+hipError_t launch_bfv_decode(const DevParams& p, const BfvConsts& k, const uint64_t* pt, uint32_t batch, int64_t* m,
                              hipStream_t s);
 
 // element-wise steps alone (kernels_elementwise.hip)

@@ -1,0 +1,131 @@
+// Host-side logic of the library, checked on the CPU: the serving budget's
+// first-fit arena, the mixed-plan unit tables, and the chi sampler's bucket
+// table against the count it stands for.  Prints "ok" and exits 0 on success.
+#include <stdint.h>
+#include <stdio.h>
+
+#include <algorithm>
+#include <random>
+#include <set>
+#include <vector>
+
+#include "arena.h"
+#include "zinc_internal.h"
+
+#define CHECK(c)                                                     \
+    do {                                                             \
+        if (!(c)) {                                                  \
+            fprintf(stderr, "check failed at line %d: %s\n", __LINE__, #c); \
+            return 1;                                                \
+        }                                                            \
+    } while (0)
+
+static int test_arena() {
+    std::mt19937_64 rng(1);
+    const uint64_t size = 1 << 20;
+    zinc::Arena a(size);
+    struct Block { uint64_t off, bytes; };
+    std::vector<Block> live;
+    for (int step = 0; step < 20000; ++step) {
+        if (live.empty() || rng() % 3) {
+            const uint64_t bytes = 1 + rng() % 40000;
+            uint64_t off = 0;
+            if (a.alloc(bytes, &off)) {
+                const uint64_t r = (bytes + 255) & ~255ull;
+                CHECK(off % 256 == 0 && off + r <= size);
+                for (const Block& b : live) CHECK(off + r <= b.off || b.off + ((b.bytes + 255) & ~255ull) <= off);
+                live.push_back({off, bytes});
+            }
+        } else {
+            const size_t i = rng() % live.size();
+            a.release(live[i].off, live[i].bytes);
+            live.erase(live.begin() + (long)i);
+        }
+        uint64_t used = 0;
+        for (const Block& b : live) used += (b.bytes + 255) & ~255ull;
+        CHECK(a.used() == used);
+    }
+    for (const Block& b : live) a.release(b.off, b.bytes);
+    uint64_t off = 1;
+    CHECK(a.used() == 0 && a.alloc(size, &off) && off == 0);   // everything merged back
+    return 0;
+}
+
+static int test_plan_tables() {
+    const uint32_t logs[4] = {14, 12, 15, 13}, limbs[4] = {7, 2, 14, 3};
+    std::vector<zinc_ctx> ctx(4);
+    std::vector<zinc_ctx*> cp;
+    for (int c = 0; c < 4; ++c) {
+        ctx[c].log_n = logs[c];
+        ctx[c].n = 1u << logs[c];
+        ctx[c].L = limbs[c];
+        cp.push_back(&ctx[c]);
+    }
+    std::mt19937 rng(2);
+    std::vector<zinc_item> items;
+    for (uint32_t i = 0; i < 301; ++i)
+        items.push_back(zinc_item{(uint32_t)(rng() % 4), 0u, 1000ull * i, 7000ull * i, 5ull * i + 1});
+    std::vector<zinc::PlanItem> di;
+    std::vector<zinc::PlanUnit> un;
+    const uint64_t dummy = zinc::build_plan_tables(cp.data(), 4, items.data(), (uint32_t)items.size(), di, un);
+    CHECK(dummy <= zinc::plan_dummy_words(cp.data(), 4));
+    std::multiset<uint64_t> seen;
+    double last_cost = 1e300;
+    for (const zinc::PlanUnit& u : un) {
+        const zinc_ctx& c = ctx[u.ctx];
+        CHECK(u.log_n == c.log_n && u.count == zinc::plan_units_per_group(c.log_n));
+        const double cost = (double)c.L * c.n * c.log_n;
+        CHECK(cost <= last_cost);                        // longest units first
+        last_cost = cost;
+        for (uint32_t k = 0; k < u.count; ++k) {
+            const zinc::PlanItem& it = di[u.first + k];
+            CHECK(it.ctx == u.ctx);
+            if (it.dummy) CHECK(it.ct_off + 2ull * c.L * c.n <= dummy);
+            else seen.insert(it.ct_id);
+        }
+        CHECK(!di[u.first].dummy);                       // a unit starts with a real item
+    }
+    CHECK(seen.size() == items.size());
+    for (const zinc_item& it : items) CHECK(seen.count(it.ct_id) == 1);
+    return 0;
+}
+
+static int test_gaussian_buckets() {
+    uint64_t cdt[zinc::kCdtLen], bucket[zinc::kCdtBuckets];
+    zinc::gaussian_cdt(3.2, cdt);
+    zinc::gaussian_buckets(cdt, bucket);
+    std::vector<uint64_t> us;
+    std::mt19937_64 rng(3);
+    for (int i = 0; i < 200000; ++i) us.push_back(rng());
+    for (int i = 0; i < zinc::kCdtLen; ++i)
+        for (int d = -1; d <= 1; ++d) us.push_back(cdt[i] + (uint64_t)(int64_t)d);
+    for (uint64_t b = 0; b < 256; ++b) {
+        us.push_back(b << 56);
+        us.push_back(((b + 1) << 56) - 1);
+    }
+    int fallback = 0;
+    for (uint64_t u : us) {
+        int count = 0;
+        for (int i = 0; i < zinc::kCdtLen; ++i) count += u >= cdt[i];
+        const uint64_t e = bucket[u >> 56];
+        if (e >> 63) {
+            ++fallback;
+            continue;
+        }
+        const uint64_t thr = (u & 0xFF00000000000000ull) | (e & 0x00FFFFFFFFFFFFFFull);
+        CHECK((int)((e >> 56) & 63) + (u >= thr ? 1 : 0) == count);
+    }
+    int flagged = 0;
+    for (int b = 0; b < 256; ++b) flagged += (int)(bucket[b] >> 63);
+    CHECK(flagged == 2 && (bucket[0] >> 63) && (bucket[255] >> 63));
+    CHECK(fallback > 0);
+    return 0;
+}
+
+int main() {
+    if (test_arena()) return 1;
+    if (test_plan_tables()) return 1;
+    if (test_gaussian_buckets()) return 1;
+    printf("ok\n");
+    return 0;
+}

@@ -52,7 +52,7 @@ class _Params(ctypes.Structure):
     _fields_ = [("log_n", ctypes.c_uint32), ("n_moduli", ctypes.c_uint32),
                 ("seed", ctypes.c_uint64), ("scale", ctypes.c_double),
                 ("q", ctypes.c_uint64 * 32), ("psi", ctypes.c_uint64 * 32),
-                ("cdt", ctypes.c_uint64 * CDT_LEN)]
+                ("cdt", ctypes.c_uint64 * CDT_LEN), ("noise_t", ctypes.c_uint64)]
 
 
 _lib = None
@@ -157,7 +157,7 @@ class Params:
     Delta, scheme seed.  L = M - 1 data limbs."""
 
     def __init__(self, log_n: int, bits=None, scale: float = 2.0 ** 40, seed: int = 0,
-                 moduli=None, sigma: float = 3.2):
+                 moduli=None, sigma: float = 3.2, bgv_t: int = 1):
         self.log_n = log_n
         self.n = 1 << log_n
         self.moduli = list(moduli) if moduli is not None else choose_moduli(log_n, bits)
@@ -174,6 +174,8 @@ class Params:
             s.psi[i] = self.psi[i]
         for i in range(CDT_LEN):
             s.cdt[i] = int(self.cdt[i])
+        self.noise_t = int(bgv_t)            # BGV: errors scaled by the plaintext modulus t
+        s.noise_t = self.noise_t
         self._c = s
 
     @property
@@ -379,6 +381,21 @@ def bfv_decode(P: Params, t: int, pt) -> np.ndarray:
     for k in range(P.n):
         x = sum(int(pt[l][k]) * basis[l] for l in range(len(qs))) % Q
         r = ((2 * t * x + Q) // (2 * Q)) % t
+        out.append(r - t if r > t // 2 else r)
+    return np.array(out, dtype=np.int64)
+
+
+def bgv_encode(P: Params, t: int, m) -> np.ndarray:
+    """BGV plaintext: residues of (m mod t) per data limb, [L][N]."""
+    return np.array([[(int(x) % t) % int(q) for x in m] for q in P.data_moduli], dtype=np.uint64)
+
+
+def bgv_decode(P: Params, t: int, pt) -> np.ndarray:
+    """BGV decoding (Eq. 13): the centred CRT value of the decrypted residues,
+    reduced mod t and centred to (-t/2, t/2]."""
+    out = []
+    for x in crt_centered(P, pt):
+        r = x % t
         out.append(r - t if r > t // 2 else r)
     return np.array(out, dtype=np.int64)
 

@@ -282,7 +282,15 @@ typedef struct {
     uint64_t q[32];
     uint64_t psi[32];
     uint64_t cdt[38];
+    uint64_t noise_t;        /* BGV (Eq. 13): every error polynomial is scaled by t;
+                                1 for CKKS and BFV */
 } oracle_params;
+
+/* residue of a Gaussian error coefficient as the scheme uses it: x, or t x
+ * for BGV (Eq. 13 scales the errors of the key, of Enc and of Zinc's e') */
+static uint64_t noise_mod(const oracle_params* p, int64_t x, uint64_t q) {
+    return smod(x * (int64_t)(p->noise_t ? p->noise_t : 1), q);
+}
 
 /* Gen (Eq. 7): s <- R_2, a <- R_q, e <- chi;  pk1 = [-a s + e]_q, pk2 = a.
  * Outputs: s_hat [M][N] (NTT domain), pk [2][M][N] (NTT domain). */
@@ -301,7 +309,7 @@ void oracle_keygen(const oracle_params* p, uint64_t* s_hat, uint64_t* pk) {
         for (uint32_t k = 0; k < n; k++) sh[k] = smod(s[k], q);
         oracle_ntt_forward(sh, p->log_n, q, p->psi[l]);
         oracle_sample_uniform(p->seed, ORACLE_KEY_ID, TAG_A, l, n, q, pk2);  /* a, NTT domain */
-        for (uint32_t k = 0; k < n; k++) tmp[k] = smod(e[k], q);
+        for (uint32_t k = 0; k < n; k++) tmp[k] = noise_mod(p, e[k], q);
         oracle_ntt_forward(tmp, p->log_n, q, p->psi[l]);
         for (uint32_t k = 0; k < n; k++)
             pk1[k] = addmod(submod(0, mulmod(pk2[k], sh[k], q), q), tmp[k], q);
@@ -330,9 +338,9 @@ void oracle_encrypt_vanilla(const oracle_params* p, const uint64_t* pk, const ui
         uint64_t* c2 = ct + ((size_t)L + l) * n;
         for (uint32_t k = 0; k < n; k++) uh[k] = smod(u[k], q);
         oracle_ntt_forward(uh, p->log_n, q, p->psi[l]);
-        for (uint32_t k = 0; k < n; k++) c1[k] = addmod(pt[(size_t)l * n + k], smod(e1[k], q), q);
+        for (uint32_t k = 0; k < n; k++) c1[k] = addmod(pt[(size_t)l * n + k], noise_mod(p, e1[k], q), q);
         oracle_ntt_forward(c1, p->log_n, q, p->psi[l]);
-        for (uint32_t k = 0; k < n; k++) c2[k] = smod(e2[k], q);
+        for (uint32_t k = 0; k < n; k++) c2[k] = noise_mod(p, e2[k], q);
         oracle_ntt_forward(c2, p->log_n, q, p->psi[l]);
         for (uint32_t k = 0; k < n; k++) {
             c1[k] = addmod(mulmod(pk1[k], uh[k], q), c1[k], q);
@@ -375,7 +383,7 @@ void oracle_encrypt_vanilla_sp(const oracle_params* p, const uint64_t* pk, const
         for (int j = 0; j < 2; j++) {
             uint64_t* aj = a + ((size_t)j * M + l) * n;
             const uint64_t* pkj = pk + ((size_t)j * M + l) * n;
-            for (uint32_t k = 0; k < n; k++) aj[k] = smod(e[j][k], q);
+            for (uint32_t k = 0; k < n; k++) aj[k] = noise_mod(p, e[j][k], q);
             oracle_ntt_forward(aj, p->log_n, q, p->psi[l]);
             for (uint32_t k = 0; k < n; k++) aj[k] = addmod(mulmod(pkj[k], uh[k], q), aj[k], q);
         }
@@ -437,10 +445,10 @@ void oracle_encrypt_zinc(const oracle_params* p, const uint64_t* zero, const uin
         oracle_ntt_forward(mh, p->log_n, q, p->psi[l]);
         for (uint32_t k = 0; k < n; k++) { c1[k] = addmod(z1[k], mh[k], q); c2[k] = z2[k]; }
         /* steps 2-3: add fresh e1', e2' */
-        for (uint32_t k = 0; k < n; k++) eh[k] = smod(e1[k], q);
+        for (uint32_t k = 0; k < n; k++) eh[k] = noise_mod(p, e1[k], q);
         oracle_ntt_forward(eh, p->log_n, q, p->psi[l]);
         for (uint32_t k = 0; k < n; k++) c1[k] = addmod(c1[k], eh[k], q);
-        for (uint32_t k = 0; k < n; k++) eh[k] = smod(e2[k], q);
+        for (uint32_t k = 0; k < n; k++) eh[k] = noise_mod(p, e2[k], q);
         oracle_ntt_forward(eh, p->log_n, q, p->psi[l]);
         for (uint32_t k = 0; k < n; k++) c2[k] = addmod(c2[k], eh[k], q);
     }

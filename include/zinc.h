@@ -123,6 +123,8 @@ typedef struct zinc_info {
     uint32_t tile[2];           /* coefficients per thread of the fused kernel
                                    for vanilla [0] and Zinc [1] (see zinc_tuning) */
     uint32_t reg_epilogue;      /* see zinc_tuning                            */
+    uint64_t bgv_t;             /* BGV plaintext modulus t (zinc_set_bgv), 0
+                                   for a CKKS/BFV context                     */
 } zinc_info;
 
 /* Create a context on the current HIP device: validate the parameters, derive
@@ -215,6 +217,27 @@ zinc_status zinc_bfv_encode(zinc_ctx* ctx, uint64_t t, const int64_t* d_m, uint3
                             void* stream);
 zinc_status zinc_bfv_decode(zinc_ctx* ctx, uint64_t t, const uint64_t* d_pt, uint32_t batch, int64_t* d_m,
                             void* stream);
+
+/* BGV on the same contexts (Scheme Flexibility section, Eq. 13): every
+ * Gaussian error (the key's e, Enc's e1 and e2, Zinc's fresh e1' and e2') is
+ * multiplied by the plaintext modulus t, and the message enters unscaled.
+ * zinc_set_bgv(ctx, t) puts the context in BGV form for the next zinc_keygen
+ * and clears its keys and cached Enc(0) (keyed = precomputed = 0); t = 1
+ * returns it to the CKKS/BFV form.  t in [2, 2^32) and below every data
+ * modulus (ZINC_E_INVAL), N <= 16384 (ZINC_E_PARAM).  A BGV context encrypts
+ * residue plaintexts through zinc_encrypt (Zinc, Algorithm 1 with t-scaled
+ * errors) and zinc_encrypt_vanilla (Eq. 8 with t-scaled errors) and decrypts
+ * through zinc_decrypt; zinc_encrypt_slots, zinc_encrypt_vanilla_sp, the BFV
+ * codec, plans, servers and zinc_autotune reject it (ZINC_E_STATE).
+ * zinc_bgv_encode: int64 d_m [batch][N], any representative ->
+ * d_pt [batch][L][N] = m mod t (in [0, t)) on every limb.
+ * zinc_bgv_decode: decrypted residues d_pt [batch][L][N] -> d_m = the centred
+ * CRT value of the residues (in (-Q/2, Q/2]) mod t, centred in (-t/2, t/2]
+ * (correct while the noise t (e u + e1 + e2 s) stays below Q/2).
+ * Both: ZINC_E_STATE on a context not in BGV form. */
+zinc_status zinc_set_bgv(zinc_ctx* ctx, uint64_t t);
+zinc_status zinc_bgv_encode(zinc_ctx* ctx, const int64_t* d_m, uint32_t batch, uint64_t* d_pt, void* stream);
+zinc_status zinc_bgv_decode(zinc_ctx* ctx, const uint64_t* d_pt, uint32_t batch, int64_t* d_m, void* stream);
 
 /* The element-wise step of Zinc encryption alone (Algorithm 1's additions, in
  * the NTT domain where the cached Enc(0) is kept), for callers that compute

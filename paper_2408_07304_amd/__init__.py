@@ -45,7 +45,7 @@ class zinc_info(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("cdt", ctypes.c_uint64 * 38),
                 ("plaintext_bytes", ctypes.c_size_t), ("ciphertext_bytes", ctypes.c_size_t),
                 ("keyed", ctypes.c_int), ("precomputed", ctypes.c_int), ("ntt_fp64_mask", ctypes.c_uint32),
-                ("tile", ctypes.c_uint32 * 2), ("reg_epilogue", ctypes.c_uint32)]
+                ("tile", ctypes.c_uint32 * 2), ("reg_epilogue", ctypes.c_uint32), ("bgv_t", ctypes.c_uint64)]
 
 
 class zinc_tuning(ctypes.Structure):
@@ -99,6 +99,9 @@ _SIGS = {
     "zinc_encrypt_vanilla_sp": (ctypes.c_int, [_vp, _vp, _u32, _vp, _vp, _vp]),
     "zinc_bfv_encode": (ctypes.c_int, [_vp, ctypes.c_uint64, _vp, _u32, _vp, _vp]),
     "zinc_bfv_decode": (ctypes.c_int, [_vp, ctypes.c_uint64, _vp, _u32, _vp, _vp]),
+    "zinc_set_bgv": (ctypes.c_int, [_vp, ctypes.c_uint64]),
+    "zinc_bgv_encode": (ctypes.c_int, [_vp, _vp, _u32, _vp, _vp]),
+    "zinc_bgv_decode": (ctypes.c_int, [_vp, _vp, _u32, _vp, _vp]),
     "zinc_encrypt_slots": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _u32, _u32, _vp, _vp, _vp]),
     "zinc_decrypt": (ctypes.c_int, [_vp, _vp, _u32, _vp, _vp]),
     "zinc_decode": (ctypes.c_int, [_vp, _vp, _u32, _vp, _vp]),
@@ -234,7 +237,7 @@ class Context:
                 "plaintext_bytes": int(i.plaintext_bytes), "ciphertext_bytes": int(i.ciphertext_bytes),
                 "keyed": bool(i.keyed), "precomputed": bool(i.precomputed),
                 "ntt_fp64_mask": int(i.ntt_fp64_mask), "tile": [int(i.tile[0]), int(i.tile[1])],
-                "reg_epilogue": int(i.reg_epilogue)}
+                "reg_epilogue": int(i.reg_epilogue), "bgv_t": int(i.bgv_t)}
 
     # -- tuning (speed only; results are identical for every choice) ---------
     def set_tuning(self, tile_vanilla: int, tile_zinc: int, ntt_fp64_mask: int, reg_epilogue: int = 0):
@@ -290,6 +293,20 @@ class Context:
     def bfv_decode(self, t: int, pt, out, stream=None):
         """Decrypted residues -> BFV plaintexts (int64, centred mod t)."""
         _check(load_library().zinc_bfv_decode(self.handle, int(t), _ptr(pt), pt.shape[0], _ptr(out), _stream(stream)))
+        return out
+
+    def set_bgv(self, t: int):
+        """BGV form (errors scaled by t) from the next keygen; t = 1 undoes it."""
+        _check(load_library().zinc_set_bgv(self.handle, int(t)))
+
+    def bgv_encode(self, m, out, stream=None):
+        """BGV plaintexts (int64 [batch][N]) -> residues of m mod t."""
+        _check(load_library().zinc_bgv_encode(self.handle, _ptr(m), m.shape[0], _ptr(out), _stream(stream)))
+        return out
+
+    def bgv_decode(self, pt, out, stream=None):
+        """Decrypted residues -> BGV plaintexts (int64, centred mod t)."""
+        _check(load_library().zinc_bgv_decode(self.handle, _ptr(pt), pt.shape[0], _ptr(out), _stream(stream)))
         return out
 
     def encrypt(self, pt, ct_ids, out, stream=None):

@@ -203,6 +203,7 @@ zinc_status zinc_ctx_create(const zinc_params* p, zinc_ctx** out) {
     d.L = c->L;
     d.seed = c->seed;
     d.scale = c->scale;
+    d.noise_t = 1;
     d.limbs = reinterpret_cast<const LimbConst*>(base + o_limbs);
     d.tw = reinterpret_cast<const uint64_t*>(base + o_tw);
     d.itw = reinterpret_cast<const uint64_t*>(base + o_itw);
@@ -253,6 +254,7 @@ zinc_status zinc_ctx_info(const zinc_ctx* c, zinc_info* o) {
     o->tile[0] = c->tile[0];
     o->tile[1] = c->tile[1];
     o->reg_epilogue = c->reg_epilogue;
+    o->bgv_t = c->dev.noise_t > 1 ? c->dev.noise_t : 0;
     return ZINC_OK;
 }
 
@@ -359,6 +361,7 @@ zinc_status zinc_encrypt_slots(zinc_ctx* c, int scheme, const double* slots, uin
     if (scheme != ZINC_SCHEME_VANILLA && scheme != ZINC_SCHEME_ZINC && scheme != ZINC_SCHEME_VANILLA_SP)
         return fail(ZINC_E_INVAL, "zinc_encrypt_slots: scheme must be 0 (vanilla), 1 (zinc) or 2 (vanilla_sp)");
     if (!c->keyed) return fail(ZINC_E_STATE, "zinc_encrypt_slots before zinc_keygen");
+    if (c->dev.noise_t > 1) return fail(ZINC_E_STATE, "zinc_encrypt_slots: a BGV context encrypts integer plaintexts");
     if (scheme == ZINC_SCHEME_ZINC && !c->precomputed)
         return fail(ZINC_E_STATE, "zinc_encrypt_slots (zinc) before zinc_precompute");
     if (n_slots > c->n / 2) return fail(ZINC_E_RANGE, "zinc_encrypt_slots: n_slots exceeds N/2");
@@ -379,6 +382,7 @@ zinc_status zinc_encrypt_vanilla_sp(zinc_ctx* c, const uint64_t* pt, uint32_t ba
                                     uint64_t* ct, void* stream) {
     if (!c) return fail(ZINC_E_INVAL, "zinc_encrypt_vanilla_sp: null context");
     if (!c->keyed) return fail(ZINC_E_STATE, "zinc_encrypt_vanilla_sp before zinc_keygen");
+    if (c->dev.noise_t > 1) return fail(ZINC_E_STATE, "zinc_encrypt_vanilla_sp: not built for BGV contexts");
     if (zinc_status s = check_batch("zinc_encrypt_vanilla_sp", batch, {pt, ids, ct})) return s;
     if (batch == 0) return ZINC_OK;
     return encrypt_sp(c, false, nullptr, 0, pt, batch, ids, ct, stream);
@@ -386,6 +390,7 @@ zinc_status zinc_encrypt_vanilla_sp(zinc_ctx* c, const uint64_t* pt, uint32_t ba
 
 // Constants of the BFV encoding / decoding for plaintext modulus t.
 static zinc_status bfv_consts(const zinc_ctx* c, uint64_t t, BfvConsts* k, const char* fn) {
+    if (c->dev.noise_t > 1) return fail(ZINC_E_STATE, std::string(fn) + ": the context is in BGV form");
     if (t < 2 || t >= (1ull << 32)) return fail(ZINC_E_INVAL, std::string(fn) + ": t must be in [2, 2^32)");
     const uint32_t L = c->L;
     for (uint32_t l = 0; l < L; ++l)
@@ -427,6 +432,63 @@ zinc_status zinc_bfv_decode(zinc_ctx* c, uint64_t t, const uint64_t* pt, uint32_
     if (zinc_status s = bfv_consts(c, t, &k, "zinc_bfv_decode")) return s;
     if (batch == 0) return ZINC_OK;
     return launched(launch_bfv_decode(c->dev, k, pt, batch, m, (hipStream_t)stream), "BFV decode launch");
+}
+
+// BGV (Eq. 13): the plaintext modulus scales every error from the next keygen.
+zinc_status zinc_set_bgv(zinc_ctx* c, uint64_t t) {
+    if (!c) return fail(ZINC_E_INVAL, "zinc_set_bgv: null context");
+    if (t != 1) {
+        if (t < 2 || t >= (1ull << 32)) return fail(ZINC_E_INVAL, "zinc_set_bgv: t must be 1 or in [2, 2^32)");
+        for (uint32_t l = 0; l < c->L; ++l)
+            if (t >= c->q[l]) return fail(ZINC_E_INVAL, "zinc_set_bgv: t must be below every data modulus");
+        if (c->log_n == 15) return fail(ZINC_E_PARAM, "zinc_set_bgv: BGV is built for N <= 16384");
+    }
+    c->dev.noise_t = t;
+    c->keyed = false;
+    c->precomputed = false;
+    return ZINC_OK;
+}
+
+zinc_status zinc_bgv_encode(zinc_ctx* c, const int64_t* m, uint32_t batch, uint64_t* pt, void* stream) {
+    if (!c) return fail(ZINC_E_INVAL, "zinc_bgv_encode: null context");
+    if (c->dev.noise_t < 2) return fail(ZINC_E_STATE, "zinc_bgv_encode: the context is not in BGV form");
+    if (zinc_status s = check_batch("zinc_bgv_encode", batch, {m, pt})) return s;
+    if (batch == 0) return ZINC_OK;
+    BfvConsts k;                                   // the BFV encoder with Delta = 1: m mod t on every limb
+    std::memset(&k, 0, sizeof(k));
+    k.t = c->dev.noise_t;
+    for (uint32_t l = 0; l < c->L; ++l) {
+        k.delta[l] = 1;
+        k.delta_sh[l] = shoup_companion(1, c->q[l]);
+    }
+    return launched(launch_bfv_encode(c->dev, k, m, batch, pt, (hipStream_t)stream), "BGV encode launch");
+}
+
+zinc_status zinc_bgv_decode(zinc_ctx* c, const uint64_t* pt, uint32_t batch, int64_t* m, void* stream) {
+    if (!c) return fail(ZINC_E_INVAL, "zinc_bgv_decode: null context");
+    if (c->dev.noise_t < 2) return fail(ZINC_E_STATE, "zinc_bgv_decode: the context is not in BGV form");
+    if (zinc_status s = check_batch("zinc_bgv_decode", batch, {pt, m})) return s;
+    if (batch == 0) return ZINC_OK;
+    const uint64_t t = c->dev.noise_t;
+    const uint32_t L = c->L;
+    BgvConsts k;
+    std::memset(&k, 0, sizeof(k));
+    k.t = t;
+    k.q_mod_t = 1 % t;
+    for (uint32_t l = 0; l < L; ++l) k.q_mod_t = (uint64_t)((unsigned __int128)k.q_mod_t * (c->q[l] % t) % t);
+    for (uint32_t l = 0; l < L; ++l) {
+        const uint64_t q = c->q[l];
+        uint64_t prod = 1, prod_t = 1 % t;                  // (Q / q_l) mod q_l and mod t
+        for (uint32_t j = 0; j < L; ++j)
+            if (j != l) {
+                prod = mulmod_host(prod, c->q[j] % q, q);
+                prod_t = (uint64_t)((unsigned __int128)prod_t * (c->q[j] % t) % t);
+            }
+        k.qt[l] = powmod_host(prod, q - 2, q);
+        k.qt_sh[l] = shoup_companion(k.qt[l], q);
+        k.qhat_mod_t[l] = prod_t;
+    }
+    return launched(launch_bgv_decode(c->dev, k, pt, batch, m, (hipStream_t)stream), "BGV decode launch");
 }
 
 zinc_status zinc_elementwise_zinc(zinc_ctx* c, const uint64_t* hat, uint32_t batch, uint64_t* ct, void* stream) {

@@ -13,7 +13,7 @@ namespace zinc {
 // ---------------------------------------------------------------------------
 // encryption
 // ---------------------------------------------------------------------------
-template <int LOGN, int SCHEME, bool FROM_SLOTS>
+template <int LOGN, int SCHEME, bool FROM_SLOTS, bool BGV = false>
 __global__ void __launch_bounds__(Cfg<LOGN>::G::T) __attribute__((amdgpu_waves_per_eu(4)))
 k_encrypt(DevParams p, EncArgs a) {
     using G = typename Cfg<LOGN>::G;
@@ -24,7 +24,7 @@ k_encrypt(DevParams p, EncArgs a) {
     const uint32_t b = blockIdx.x;
     load_cdt(tab, p.cdt, t);
     const uint32_t L = p.L;
-    encrypt_item<LOGN, SCHEME, FROM_SLOTS>(p, a.slots + (size_t)b * a.n_slots, a.n_slots,
+    encrypt_item<LOGN, SCHEME, FROM_SLOTS, BGV>(p, a.slots + (size_t)b * a.n_slots, a.n_slots,
                                           a.pt + (size_t)b * L * N, a.ct_ids[b], a.ct + (size_t)b * 2 * L * N,
                                           lds, tab, t);
 }
@@ -63,8 +63,10 @@ __global__ void __launch_bounds__(Cfg<LOGN>::G::T) k_keygen(DevParams p, u64* sk
         sk[(size_t)l * N + k] = sh[i];
         sk_sh[(size_t)l * N + k] = shs[i];
     }
+    const u64 et = p.noise_t > 1 ? p.noise_t : 0;      // BGV: the error is t e (Eq. 13)
 #pragma unroll
-    for (int c = 0; c < R; ++c) v[c] = small_mod(e.get(c), q);
+    for (int c = 0; c < R; ++c)
+        v[c] = et ? reduce_signed((long long)e.get(c) * (long long)et, lc) : small_mod(e.get(c), q);
     ntt_fwd<G>(v, lds, p.tw, l, q, q2, t);
     to_natural<G>(lds, v, t);
 #pragma unroll
@@ -271,15 +273,20 @@ hipError_t launch_encrypt_pt(const DevParams& p, int scheme, const uint64_t* pt,
                              const uint64_t* ct_ids, uint64_t* ct, hipStream_t s) {
     if (p.log_n == 15) return launch_split_encrypt(p, scheme, false, nullptr, 0, pt, batch, ct_ids, ct, s);
     EncArgs a{nullptr, 0, (const u64*)pt, (const u64*)ct_ids, (u64*)ct};
-#define F(LN)                                                                                          \
-    if (scheme == ZINC_SCHEME_ZINC)                                                                    \
-        hipLaunchKernelGGL((k_encrypt<LN, ZINC_SCHEME_ZINC, false>), dim3(batch), dim3(Cfg<LN>::G::T), \
-                           0, s, p, a);                                                                \
-    else                                                                                               \
-        hipLaunchKernelGGL((k_encrypt<LN, ZINC_SCHEME_VANILLA, false>), dim3(batch),                  \
-                           dim3(Cfg<LN>::G::T), 0, s, p, a)
+    const bool bgv = p.noise_t > 1;
+#define G_(LN, SCH, B) \
+    hipLaunchKernelGGL((k_encrypt<LN, SCH, false, B>), dim3(batch), dim3(Cfg<LN>::G::T), 0, s, p, a)
+#define F(LN)                                        \
+    if (scheme == ZINC_SCHEME_ZINC) {                \
+        if (bgv) G_(LN, ZINC_SCHEME_ZINC, true);     \
+        else G_(LN, ZINC_SCHEME_ZINC, false);        \
+    } else {                                         \
+        if (bgv) G_(LN, ZINC_SCHEME_VANILLA, true);  \
+        else G_(LN, ZINC_SCHEME_VANILLA, false);     \
+    }
     ZINC_DISPATCH_LOGN(p.log_n, F)
 #undef F
+#undef G_
     return hipGetLastError();
 }
 

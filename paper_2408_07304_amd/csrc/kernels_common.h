@@ -143,19 +143,37 @@ __device__ __forceinline__ void transform_store(const LimbNtt<G>& nt, uint32_t t
     }
 }
 
+// A Gaussian error coefficient x as the scheme adds it, for the integer and the
+// FP64 transforms: x itself, or t x under BGV (Eq. 13 scales every error by
+// the plaintext modulus t).  |x| < 64 and t < 2^32, so t x is below 2^38 and
+// exact in a double.
+template <bool BGV>
+__device__ __forceinline__ u64 noise_ri(int x, u64 t, const LimbConst& lc) {     // [0, q)
+    if constexpr (BGV) return reduce_signed((long long)x * (long long)t, lc);
+    else return small_mod(x, lc.q);
+}
+template <bool BGV>
+__device__ __forceinline__ double noise_rf(int x, u64 t, const LimbConst& lc) {  // |value| <= q/2 + 64
+    if constexpr (BGV) return fp_round_reduce((double)x * (double)t, lc.qd, lc.qinv);
+    else return (double)x;
+}
+
 // Pass-0 message input of limb l: (m + e) with m read back from the stash
-// (encoded slots) or from the caller's plaintext residues.
-template <class G, bool FROM_SLOTS>
+// (encoded slots) or from the caller's plaintext residues.  BGV (plaintext
+// residues only): the error is t e.
+template <class G, bool FROM_SLOTS, bool BGV = false>
 struct MessageIn {
     const long long* stash;
     const u64* pt;
     Packed8<G::R> e;
     LimbConst lc;
     uint32_t tp0;
+    u64 noise_t;
+    static_assert(!(FROM_SLOTS && BGV), "BGV encrypts integer plaintexts");
     __device__ __forceinline__ u64 ri(int c) const {       // residue in [0, 2q)
         const uint32_t k = tp0 | G::cpart(0, c);
         if constexpr (FROM_SLOTS) return reduce_signed(stash[k] + e.get(c), lc);
-        else return pt[k] + small_mod(e.get(c), lc.q);
+        else return pt[k] + noise_ri<BGV>(e.get(c), noise_t, lc);
     }
     __device__ __forceinline__ double rf(int c) const {    // |value| <= q
         const uint32_t k = tp0 | G::cpart(0, c);
@@ -165,6 +183,9 @@ struct MessageIn {
             const long long x = stash[k] + e.get(c);
             if (x > -(1ll << 52) && x < (1ll << 52)) return fp_round_reduce((double)x, lc.qd, lc.qinv);
             return u64_to_fp(reduce_signed(x, lc));
+        } else if constexpr (BGV) {
+            // pt < 2^50 on FP64 limbs and |t e| < 2^38: the sum is exact
+            return fp_round_reduce(u64_to_fp(pt[k]) + (double)e.get(c) * (double)noise_t, lc.qd, lc.qinv);
         } else {
             return u64_to_fp(pt[k]) + (double)e.get(c);
         }
@@ -183,7 +204,10 @@ struct MessageIn {
 // the group's exchange buffer (LdsWords<N> words), tab the chi table in LDS.
 // G is the thread geometry: any Geom<LOGN, LOGT> with at least 4 coefficients
 // per thread (the default is Cfg<LOGN>::G, 16 per thread).
-template <class G, int SCHEME, bool FROM_SLOTS, bool REG_EPI = false>
+//
+// BGV = true (integer plaintexts only): every Gaussian error is scaled by the
+// plaintext modulus p.noise_t (Eq. 13).
+template <class G, int SCHEME, bool FROM_SLOTS, bool REG_EPI = false, bool BGV = false>
 __device__ __forceinline__ void encrypt_item_g(const DevParams& p, const double* slots, uint32_t n_slots,
                                                const u64* pt, u64 ct_id, u64* ct, u64* lds, const u64* tab,
                                                uint32_t t) {
@@ -207,7 +231,8 @@ __device__ __forceinline__ void encrypt_item_g(const DevParams& p, const double*
         for (uint32_t l = 0; l < L; ++l) {
             const LimbConst lc = p.limbs[l];
             const LimbNtt<G> nt{p, lc, l, lds, t};
-            const MessageIn<G, FROM_SLOTS> msg{stash, pt + (size_t)l * N, e1.fresh(), lc, G::tpart(0, opaque_tid(t))};
+            const MessageIn<G, FROM_SLOTS, BGV> msg{stash, pt + (size_t)l * N, e1.fresh(), lc,
+                                                    G::tpart(0, opaque_tid(t)), p.noise_t};
             // c1 = zero1 + NTT(m + e1')
             const u64* z1 = p.zero + (size_t)l * N;
             u64* c1 = ct + (size_t)l * N;
@@ -220,8 +245,8 @@ __device__ __forceinline__ void encrypt_item_g(const DevParams& p, const double*
             const Packed8<R> e2l = e2.fresh();
             const u64* z2 = p.zero + (size_t)(L + l) * N;
             u64* c2 = ct + (size_t)(L + l) * N;
-            transform_store<REG_EPI>(nt, t, [&](int c) { return small_mod(e2l.get(c), lc.q); },
-                                     [&](int c) { return (double)e2l.get(c); },
+            transform_store<REG_EPI>(nt, t, [&](int c) { return noise_ri<BGV>(e2l.get(c), p.noise_t, lc); },
+                                     [&](int c) { return noise_rf<BGV>(e2l.get(c), p.noise_t, lc); },
                                      [&](uint32_t k, u64 a, u64 b) {
                                          const u64x2 z = load_pair(z2 + k);
                                          store_pair(c2 + k, addmod(a, z.x, lc.q), addmod(b, z.y, lc.q));
@@ -245,7 +270,8 @@ __device__ __forceinline__ void encrypt_item_g(const DevParams& p, const double*
                                      [&](int c) { return (double)ul.get(c); },
                                      [&](uint32_t k, u64 a, u64 b) { store_pair(c2 + k, a, b); });
             // c1 = pk1 u_hat + NTT(m + e1)
-            const MessageIn<G, FROM_SLOTS> msg{stash, pt + (size_t)l * N, e1.fresh(), lc, G::tpart(0, opaque_tid(t))};
+            const MessageIn<G, FROM_SLOTS, BGV> msg{stash, pt + (size_t)l * N, e1.fresh(), lc,
+                                                    G::tpart(0, opaque_tid(t)), p.noise_t};
             const u64* pk1 = p.pk + (size_t)l * N;
             const u64* pk1s = p.pk_sh + (size_t)l * N;
             transform_store<REG_EPI>(nt, t, [&](int c) { return msg.ri(c); }, [&](int c) { return msg.rf(c); },
@@ -259,8 +285,8 @@ __device__ __forceinline__ void encrypt_item_g(const DevParams& p, const double*
             const Packed8<R> e2l = e2.fresh();
             const u64* pk2 = p.pk + (size_t)(M + l) * N;
             const u64* pk2s = p.pk_sh + (size_t)(M + l) * N;
-            transform_store<REG_EPI>(nt, t, [&](int c) { return small_mod(e2l.get(c), lc.q); },
-                                     [&](int c) { return (double)e2l.get(c); },
+            transform_store<REG_EPI>(nt, t, [&](int c) { return noise_ri<BGV>(e2l.get(c), p.noise_t, lc); },
+                                     [&](int c) { return noise_rf<BGV>(e2l.get(c), p.noise_t, lc); },
                                      [&](uint32_t k, u64 a, u64 b) {
                                          const u64x2 u2 = load_pair(c2 + k), w = load_pair(pk2 + k),
                                                      ws = load_pair(pk2s + k);
@@ -271,11 +297,12 @@ __device__ __forceinline__ void encrypt_item_g(const DevParams& p, const double*
     }
 }
 
-template <int LOGN, int SCHEME, bool FROM_SLOTS>
+template <int LOGN, int SCHEME, bool FROM_SLOTS, bool BGV = false>
 __device__ __forceinline__ void encrypt_item(const DevParams& p, const double* slots, uint32_t n_slots,
                                              const u64* pt, u64 ct_id, u64* ct, u64* lds, const u64* tab,
                                              uint32_t t) {
-    encrypt_item_g<typename Cfg<LOGN>::G, SCHEME, FROM_SLOTS>(p, slots, n_slots, pt, ct_id, ct, lds, tab, t);
+    encrypt_item_g<typename Cfg<LOGN>::G, SCHEME, FROM_SLOTS, false, BGV>(p, slots, n_slots, pt, ct_id, ct, lds,
+                                                                          tab, t);
 }
 
 }  // namespace zinc

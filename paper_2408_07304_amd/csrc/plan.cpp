@@ -99,6 +99,8 @@ zinc_status zinc_plan_create(zinc_ctx* const* ctxs, uint32_t n_ctx, const zinc_i
     for (uint32_t c = 0; c < n_ctx; ++c) {
         if (!ctxs[c]) return plan_fail(ZINC_E_INVAL, "zinc_plan_create: null context");
         if (!ctxs[c]->keyed) return plan_fail(ZINC_E_STATE, "zinc_plan_create: context without keys");
+        if (ctxs[c]->dev.noise_t > 1)
+            return plan_fail(ZINC_E_STATE, "zinc_plan_create: a BGV context encrypts integer plaintexts only");
         if (scheme == ZINC_SCHEME_ZINC && !ctxs[c]->precomputed)
             return plan_fail(ZINC_E_STATE, "zinc_plan_create: context without a cached Enc(0)");
     }

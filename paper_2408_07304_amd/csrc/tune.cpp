@@ -160,6 +160,7 @@ zinc_status zinc_autotune(zinc_ctx* c, uint32_t batch, const char* cache_path, z
     if (!c || !out) return plan_fail(ZINC_E_INVAL, "zinc_autotune: null argument");
     if (batch == 0 || batch > 65536) return plan_fail(ZINC_E_INVAL, "zinc_autotune: batch must be in [1, 65536]");
     if (!c->keyed) return plan_fail(ZINC_E_STATE, "zinc_autotune before zinc_keygen");
+    if (c->dev.noise_t > 1) return plan_fail(ZINC_E_STATE, "zinc_autotune: a BGV context has no slot encryption");
     std::memset(out, 0, sizeof(*out));
     const std::string key = cache_key(c, batch);
     if (cache_path) {

@@ -45,6 +45,7 @@ struct DevParams {
     uint32_t log_n, n, M, L;
     uint64_t seed;
     double scale;
+    uint64_t noise_t;             // 1; BGV: the plaintext modulus t scaling every error (Eq. 13)
     const LimbConst* limbs;       // [M]
     const uint64_t* tw;           // [M][N][2]  (psi^brv(k), Shoup companion)
     const uint64_t* itw;          // [M][N][2]  (psi^-brv(k), Shoup companion)
@@ -72,6 +73,15 @@ struct BfvConsts {
     uint64_t b[ZINC_MAX_MODULI];          // t Qt_l mod q_l, Qt_l = (Q / q_l)^-1 mod q_l
     uint64_t b_sh[ZINC_MAX_MODULI];
     uint64_t w_mod_t[ZINC_MAX_MODULI];    // floor(t Qt_l / q_l) mod t
+};
+
+// Constants of BGV decoding for plaintext modulus t (kernels_bfv.hip).
+struct BgvConsts {
+    uint64_t t;
+    uint64_t q_mod_t;                     // Q mod t
+    uint64_t qt[ZINC_MAX_MODULI];         // Qt_l = (Q / q_l)^-1 mod q_l
+    uint64_t qt_sh[ZINC_MAX_MODULI];
+    uint64_t qhat_mod_t[ZINC_MAX_MODULI]; // (Q / q_l) mod t
 };
 
 // One ciphertext of a mixed-shape plan (device copy of a zinc_item).
@@ -168,6 +178,8 @@ hipError_t launch_encrypt_sp(const DevParams& p, bool from_slots, const double* 
 hipError_t launch_bfv_encode(const DevParams& p, const BfvConsts& k, const int64_t* m, uint32_t batch, uint64_t* pt,
                              hipStream_t s);
 hipError_t launch_bfv_decode(const DevParams& p, const BfvConsts& k, const uint64_t* pt, uint32_t batch, int64_t* m,
+                             hipStream_t s);
+hipError_t launch_bgv_decode(const DevParams& p, const BgvConsts& k, const uint64_t* pt, uint32_t batch, int64_t* m,
                              hipStream_t s);
 
 // element-wise steps alone (kernels_elementwise.hip)

@@ -1,0 +1,152 @@
+"""BGV on the GPU contexts (Scheme Flexibility section, Eq. 13: every error
+scaled by the plaintext modulus t): keys, the cached Enc(0) and Zinc and
+vanilla ciphertexts bit-exact against the oracle's BGV form, the encoding
+bit-exact, decoding equal to the oracle's exact CRT decoding, round trips, and
+the state rules of a BGV context."""
+import functools
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2408_07304_amd as zinc
+from gpu_util import empty_u64, from_dev, gpu_ctx, ids, to_dev, torch_cuda
+from paper_2408_07304_amd.workloads import PARAM_SETS
+
+pytestmark = pytest.mark.gpu
+
+CASES = [("n4096", 65537), ("n8192", 257), ("n16384", (1 << 31) - 1)]
+
+
+def say(msg):
+    print(f"[gpu] {msg}", flush=True)
+
+
+@functools.lru_cache(maxsize=None)
+def bgv_pair(name, t):
+    ps = PARAM_SETS[name]
+    say(f"BGV context {name} t={t} keygen+precompute")
+    c = zinc.context_for(ps)
+    c.set_bgv(t)
+    c.keygen()
+    c.precompute()
+    P = oracle.Params(ps.log_n, ps.bits, ps.scale, ps.seed, bgv_t=t)
+    sh, pk = oracle.keygen(P)
+    zero = oracle.zinc_precompute(P, pk)
+    return c, P, sh, pk, zero
+
+
+@pytest.mark.parametrize("name,t", CASES)
+def test_bgv_keys_and_cache_bit_exact(name, t):
+    torch_cuda()
+    c, P, sh, pk, zero = bgv_pair(name, t)
+    info = c.info()
+    assert info["bgv_t"] == t and info["keyed"] and info["precomputed"]
+    dsk, dpk, dz = empty_u64(P.M, P.n), empty_u64(2, P.M, P.n), empty_u64(2, P.L, P.n)
+    c.export_keys(dsk, dpk, dz)
+    assert np.array_equal(from_dev(dsk), sh)
+    assert np.array_equal(from_dev(dpk), pk)
+    assert np.array_equal(from_dev(dz), zero)
+
+
+@pytest.mark.parametrize("name,t", CASES)
+def test_bgv_encrypt_bit_exact_and_round_trip(name, t):
+    torch = torch_cuda()
+    c, P, sh, pk, zero = bgv_pair(name, t)
+    B = 4
+    rng = np.random.default_rng(t + P.n)
+    m = rng.integers(-(t // 2), t // 2 + 1, size=(B, P.n))
+    m[0, :5] = [0, 1, -1, t // 2, -(t // 2)]
+    m[1] = 0                                            # an empty plaintext
+    pt = empty_u64(B, P.L, P.n)
+    c.bgv_encode(to_dev(m), pt)
+    got_pt = from_dev(pt)
+    for b in range(B):
+        assert np.array_equal(got_pt[b], oracle.bgv_encode(P, t, m[b])), b
+    # residues over the whole of [0, q_l) too: the kernels take any plaintext
+    wide = np.stack([rng.integers(0, q, size=P.n, dtype=np.uint64) for q in P.data_moduli])
+    idv = [5, 0, 2 ** 40 + 3, 77]
+    for scheme in (zinc.ZINC_SCHEME_ZINC, zinc.ZINC_SCHEME_VANILLA):
+        say(f"{name} t={t} scheme={scheme}")
+        enc = c.encrypt if scheme == zinc.ZINC_SCHEME_ZINC else c.encrypt_vanilla
+        ct = empty_u64(B, 2, P.L, P.n)
+        enc(pt, ids(idv), ct)
+        got = from_dev(ct)
+        for b in (0, 3):
+            want = (oracle.encrypt_zinc(P, zero, got_pt[b], idv[b]) if scheme == zinc.ZINC_SCHEME_ZINC
+                    else oracle.encrypt_vanilla(P, pk, got_pt[b], idv[b]))
+            assert np.array_equal(got[b], want), (scheme, b)
+        ctw = empty_u64(1, 2, P.L, P.n)
+        enc(to_dev(wide[None]), ids([9]), ctw)
+        want = (oracle.encrypt_zinc(P, zero, wide, 9) if scheme == zinc.ZINC_SCHEME_ZINC
+                else oracle.encrypt_vanilla(P, pk, wide, 9))
+        assert np.array_equal(from_dev(ctw)[0], want), scheme
+        dec = empty_u64(B, P.L, P.n)
+        c.decrypt(ct, dec)
+        out = torch.empty((B, P.n), dtype=torch.int64, device="cuda")
+        c.bgv_decode(dec, out)
+        back = from_dev(out, np.int64)
+        assert np.array_equal(back, m), scheme
+        d = from_dev(dec)
+        assert np.array_equal(back[2], oracle.bgv_decode(P, t, d[2]))
+
+
+def test_bgv_decode_parity_on_arbitrary_residues():
+    """Decoding of residues that are no ciphertext's: the centred CRT value of
+    uniform residues, reduced mod t, against the oracle's big-integer lift."""
+    torch = torch_cuda()
+    c, P, sh, pk, zero = bgv_pair("n4096", 65537)
+    rng = np.random.default_rng(3)
+    r = np.stack([rng.integers(0, q, size=P.n, dtype=np.uint64) for q in P.data_moduli])
+    r[:, :4] = 0
+    r[:, 1] = 1                                         # x = 1
+    r[:, 2] = [q - 1 for q in P.data_moduli]            # x = -1
+    out = torch.empty((1, P.n), dtype=torch.int64, device="cuda")
+    c.bgv_decode(to_dev(r[None]), out)
+    got = from_dev(out, np.int64)[0]
+    assert list(got[:3]) == [0, 1, -1]
+    assert np.array_equal(got, oracle.bgv_decode(P, 65537, r))
+
+
+def test_bgv_state_rules():
+    torch = torch_cuda()
+    ps = PARAM_SETS["n4096"]
+    c = zinc.context_for(ps)
+    q0 = int(min(c.info()["moduli"][:c.L]))
+    for bad in (0, 1 << 32, q0):
+        with pytest.raises(zinc.ZincError) as e:
+            c.set_bgv(bad)
+        assert e.value.status == zinc.ZINC_E_INVAL
+    big = zinc.context_for(PARAM_SETS["n32768"])
+    with pytest.raises(zinc.ZincError) as e:
+        big.set_bgv(257)
+    assert e.value.status == zinc.ZINC_E_PARAM
+    m = torch.zeros((1, c.n), dtype=torch.int64, device="cuda")
+    pt = empty_u64(1, c.L, c.n)
+    with pytest.raises(zinc.ZincError) as e:           # not in BGV form
+        c.bgv_encode(m, pt)
+    assert e.value.status == zinc.ZINC_E_STATE
+    c.keygen()
+    c.set_bgv(257)
+    info = c.info()
+    assert info["bgv_t"] == 257 and not info["keyed"] and not info["precomputed"]
+    c.keygen()
+    c.precompute()
+    slots = to_dev(np.zeros((1, ps.slots)))
+    ct = empty_u64(1, 2, c.L, c.n)
+    for call in (lambda: c.encrypt_slots(zinc.ZINC_SCHEME_ZINC, slots, ids([1]), ct),
+                 lambda: c.encrypt_vanilla_sp(pt, ids([1]), ct),
+                 lambda: c.bfv_encode(257, m, pt),
+                 lambda: c.autotune(batch=8)):
+        with pytest.raises(zinc.ZincError) as e:
+            call()
+        assert e.value.status == zinc.ZINC_E_STATE
+    c.set_bgv(1)                                       # back to the CKKS form
+    assert c.info()["bgv_t"] == 0 and not c.info()["keyed"]
+    c.keygen()
+    ref = gpu_ctx("n4096")
+    P = ref.info()
+    dpk, rpk = empty_u64(2, P["n_moduli"], P["n"]), empty_u64(2, P["n_moduli"], P["n"])
+    c.export_keys(None, dpk, None)
+    ref.export_keys(None, rpk, None)
+    assert np.array_equal(from_dev(dpk), from_dev(rpk))

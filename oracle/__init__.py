@@ -400,6 +400,62 @@ def bgv_decode(P: Params, t: int, pt) -> np.ndarray:
     return np.array(out, dtype=np.int64)
 
 
+# ---------------------------------------------------------------------------
+# Batch (slot) encoding of BFV and BGV plaintexts.  The paper leaves encoding
+# to those schemes' own papers (Scheme Flexibility section); the batch
+# encoding used here is the standard one: for a prime t = 1 (mod 2N), Z_t[X] /
+# (X^N + 1) splits into N copies of Z_t, one per primitive 2N-th root of unity
+# zeta^e (e odd), and a plaintext m carries the slot values m(zeta^e).
+# ---------------------------------------------------------------------------
+def batch_exponents(log_n: int) -> list[int]:
+    """Slot j's evaluation point zeta^(e_j) (mod 2N): e_i = 3^i for i < N/2 and
+    e_(N/2 + i) = -3^i.  3 has order N/2 mod 2N and -1 is not a power of 3,
+    so the N exponents are the N odd residues, and X -> X^3 rotates each half
+    by one slot."""
+    n = 1 << log_n
+    two_n = 2 * n
+    pw = [pow(3, i, two_n) for i in range(n // 2)]
+    return pw + [(two_n - e) % two_n for e in pw]
+
+
+def _brv(x: int, bits: int) -> int:
+    return int(format(x, f"0{bits}b")[::-1], 2) if bits else 0
+
+
+def _batch_index(log_n: int) -> list[int]:
+    """Position of each slot in the oracle's NTT output, whose entry k is the
+    evaluation at psi^(2 brv(k) + 1) (ntt_forward)."""
+    return [_brv((e - 1) // 2, log_n) for e in batch_exponents(log_n)]
+
+
+def batch_zeta(log_n: int, t: int) -> int:
+    """zeta: the smallest primitive 2N-th root of unity mod t (the moduli's rule)."""
+    if not is_prime(t) or t % (2 << log_n) != 1:
+        raise ValueError("batch encoding needs a prime t = 1 mod 2N")
+    return find_psi(t, log_n)
+
+
+def batch_encode(log_n: int, t: int, slots) -> np.ndarray:
+    """Slot values (any integers, taken mod t) -> the coefficients in [0, t) of
+    the m in Z_t[X]/(X^N + 1) with m(zeta^(e_j)) = slots[j] mod t."""
+    hat = np.zeros(1 << log_n, dtype=np.uint64)
+    for j, k in enumerate(_batch_index(log_n)):
+        hat[k] = int(slots[j]) % t
+    return ntt_inverse(hat, log_n, t, batch_zeta(log_n, t)).astype(np.int64)
+
+
+def batch_decode(log_n: int, t: int, m) -> np.ndarray:
+    """Coefficients (any integers, taken mod t) -> slot values m(zeta^(e_j)) mod
+    t, centred to (-t/2, t/2]."""
+    a = np.array([int(x) % t for x in m], dtype=np.uint64)
+    hat = ntt_forward(a, log_n, t, batch_zeta(log_n, t))
+    out = []
+    for k in _batch_index(log_n):
+        r = int(hat[k])
+        out.append(r - t if r > t // 2 else r)
+    return np.array(out, dtype=np.int64)
+
+
 def crt_centered(P: Params, pt, limbs: int | None = None) -> list[int]:
     """Exact centred lift of RNS residues [L][N] to integers in (-Q/2, Q/2]
     (Chinese remaindering with Python integers)."""

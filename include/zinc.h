@@ -206,7 +206,7 @@ zinc_status zinc_encrypt_vanilla_sp(zinc_ctx* ctx, const uint64_t* d_pt, uint32_
  * rest of the encryption is unchanged, so zinc_encrypt (Zinc) and
  * zinc_encrypt_vanilla (Eq. 8) encrypt BFV plaintexts as they are.
  * Plaintexts: integer polynomials with coefficients in Z_t, one per ring
- * coefficient (the BFV batch encoding is not provided), int64 [batch][N],
+ * coefficient (slot vectors go through zinc_batch_encode first), int64 [batch][N],
  * any representative (reduced mod t by the encoding).
  * zinc_bfv_encode: d_m -> d_pt [batch][L][N] = Delta * m mod q_l.
  * zinc_bfv_decode: decrypted residues d_pt [batch][L][N] (zinc_decrypt) ->
@@ -238,6 +238,28 @@ zinc_status zinc_bfv_decode(zinc_ctx* ctx, uint64_t t, const uint64_t* d_pt, uin
 zinc_status zinc_set_bgv(zinc_ctx* ctx, uint64_t t);
 zinc_status zinc_bgv_encode(zinc_ctx* ctx, const int64_t* d_m, uint32_t batch, uint64_t* d_pt, void* stream);
 zinc_status zinc_bgv_decode(zinc_ctx* ctx, const uint64_t* d_pt, uint32_t batch, int64_t* d_m, void* stream);
+
+/* Batch (slot) encoding of BFV and BGV plaintexts.  The paper takes encodings
+ * from those schemes' own papers (Scheme Flexibility section); this is the
+ * standard batch encoding for a prime t = 1 (mod 2N): slot j of a plaintext m
+ * in Z_t[X]/(X^N + 1) is m(zeta^(e_j)) mod t, where zeta is the smallest
+ * primitive 2N-th root of unity mod t, e_i = 3^i and e_(N/2 + i) = -3^i
+ * (mod 2N) for i < N/2.  So X -> X^3 rotates each half of the slots by one
+ * and X -> X^-1 swaps the halves, and products of plaintexts are slot-wise.
+ * zinc_batch_encode: int64 slot values d_slots [batch][N] (any
+ * representatives) -> the coefficients d_m [batch][N] in [0, t), ready for
+ * zinc_bfv_encode or zinc_bgv_encode.
+ * zinc_batch_decode: int64 coefficients d_m [batch][N] (any representatives,
+ * e.g. zinc_bfv_decode's or zinc_bgv_decode's output) -> slot values
+ * d_slots [batch][N] in (-t/2, t/2].
+ * Input and output may be the same buffer.  t prime, t < 2^31, t = 1 mod 2N
+ * (ZINC_E_INVAL otherwise).  The first call for a given t builds its tables
+ * (20 N bytes of device memory, kept until zinc_ctx_destroy) with a
+ * synchronous upload; later calls only launch. */
+zinc_status zinc_batch_encode(zinc_ctx* ctx, uint64_t t, const int64_t* d_slots, uint32_t batch, int64_t* d_m,
+                              void* stream);
+zinc_status zinc_batch_decode(zinc_ctx* ctx, uint64_t t, const int64_t* d_m, uint32_t batch, int64_t* d_slots,
+                              void* stream);
 
 /* The element-wise step of Zinc encryption alone (Algorithm 1's additions, in
  * the NTT domain where the cached Enc(0) is kept), for callers that compute

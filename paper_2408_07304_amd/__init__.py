@@ -100,6 +100,8 @@ _SIGS = {
     "zinc_bfv_encode": (ctypes.c_int, [_vp, ctypes.c_uint64, _vp, _u32, _vp, _vp]),
     "zinc_bfv_decode": (ctypes.c_int, [_vp, ctypes.c_uint64, _vp, _u32, _vp, _vp]),
     "zinc_set_bgv": (ctypes.c_int, [_vp, ctypes.c_uint64]),
+    "zinc_batch_encode": (ctypes.c_int, [_vp, ctypes.c_uint64, _vp, _u32, _vp, _vp]),
+    "zinc_batch_decode": (ctypes.c_int, [_vp, ctypes.c_uint64, _vp, _u32, _vp, _vp]),
     "zinc_bgv_encode": (ctypes.c_int, [_vp, _vp, _u32, _vp, _vp]),
     "zinc_bgv_decode": (ctypes.c_int, [_vp, _vp, _u32, _vp, _vp]),
     "zinc_encrypt_slots": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _u32, _u32, _vp, _vp, _vp]),
@@ -307,6 +309,18 @@ class Context:
     def bgv_decode(self, pt, out, stream=None):
         """Decrypted residues -> BGV plaintexts (int64, centred mod t)."""
         _check(load_library().zinc_bgv_decode(self.handle, _ptr(pt), pt.shape[0], _ptr(out), _stream(stream)))
+        return out
+
+    def batch_encode(self, t: int, slots, out, stream=None):
+        """Slot values (int64 [batch][N]) -> BFV/BGV plaintext coefficients in [0, t)."""
+        _check(load_library().zinc_batch_encode(self.handle, int(t), _ptr(slots), slots.shape[0], _ptr(out),
+                                                _stream(stream)))
+        return out
+
+    def batch_decode(self, t: int, m, out, stream=None):
+        """Plaintext coefficients (int64 [batch][N]) -> slot values, centred mod t."""
+        _check(load_library().zinc_batch_decode(self.handle, int(t), _ptr(m), m.shape[0], _ptr(out),
+                                                _stream(stream)))
         return out
 
     def encrypt(self, pt, ct_ids, out, stream=None):

@@ -228,6 +228,7 @@ zinc_status zinc_ctx_destroy(zinc_ctx* c) {
     if (!c) return fail(ZINC_E_INVAL, "zinc_ctx_destroy: null context");
     (void)hipDeviceSynchronize();
     if (c->d_block) (void)hipFree(c->d_block);
+    for (const auto& b : c->batch_tables) (void)hipFree(b.d);
     delete c;
     return ZINC_OK;
 }
@@ -489,6 +490,82 @@ zinc_status zinc_bgv_decode(zinc_ctx* c, const uint64_t* pt, uint32_t batch, int
         k.qhat_mod_t[l] = prod_t;
     }
     return launched(launch_bgv_decode(c->dev, k, pt, batch, m, (hipStream_t)stream), "BGV decode launch");
+}
+
+// The batch-encoding tables for t, built and uploaded on first use and kept
+// (never rewritten) until the context is destroyed.
+static zinc_status batch_args(zinc_ctx* c, uint64_t t, BatchArgs* g, const char* fn) {
+    const uint32_t n = c->n, log_n = c->log_n;
+    if (t < 3 || t >= (1ull << 31) || t % (2ull * n) != 1 || !is_prime(t))
+        return fail(ZINC_E_INVAL, std::string(fn) + ": t must be a prime below 2^31 with t = 1 mod 2N");
+    const zinc_ctx::BatchTable* found = nullptr;
+    for (const auto& b : c->batch_tables)
+        if (b.t == t) found = &b;
+    if (!found) {
+        const uint64_t zeta = smallest_psi(t, log_n), zinv = powmod_host(zeta, t - 2, t);
+        std::vector<uint32_t> h((size_t)5 * n);
+        uint32_t* tw = h.data();
+        uint32_t* itw = tw + 2 * (size_t)n;
+        uint32_t* pos = itw + 2 * (size_t)n;
+        for (uint32_t k = 0; k < n; ++k) {
+            uint32_t r = 0;                                       // brv(k) over log_n bits
+            for (uint32_t b = 0; b < log_n; ++b) r |= ((k >> b) & 1u) << (log_n - 1 - b);
+            const uint64_t w = powmod_host(zeta, r, t), wi = powmod_host(zinv, r, t);
+            tw[2 * k] = (uint32_t)w;
+            tw[2 * k + 1] = (uint32_t)((w << 32) / t);
+            itw[2 * k] = (uint32_t)wi;
+            itw[2 * k + 1] = (uint32_t)((wi << 32) / t);
+        }
+        uint64_t e = 1;                                           // 3^i mod 2N
+        for (uint32_t i = 0; i < n / 2; ++i) {
+            const uint64_t es[2] = {e, 2ull * n - e};             // slots i and N/2 + i
+            for (int half = 0; half < 2; ++half) {
+                const uint32_t x = (uint32_t)((es[half] - 1) / 2);
+                uint32_t r = 0;
+                for (uint32_t b = 0; b < log_n; ++b) r |= ((x >> b) & 1u) << (log_n - 1 - b);
+                pos[i + half * (n / 2)] = r;
+            }
+            e = e * 3 % (2ull * n);
+        }
+        void* d = nullptr;
+        if (hipMalloc(&d, h.size() * 4) != hipSuccess) return fail(ZINC_E_NOMEM, std::string(fn) + ": table allocation");
+        const hipError_t ce = hipMemcpy(d, h.data(), h.size() * 4, hipMemcpyHostToDevice);
+        if (ce != hipSuccess) {
+            (void)hipFree(d);
+            return hip_fail(ce, fn);
+        }
+        const uint64_t ninv = powmod_host(n % t, t - 2, t);
+        c->batch_tables.push_back({t, d, (uint32_t)ninv, (uint32_t)((ninv << 32) / t)});
+        found = &c->batch_tables.back();
+    }
+    const uint32_t* base = static_cast<const uint32_t*>(found->d);
+    g->tw = base;
+    g->itw = base + 2 * (size_t)n;
+    g->pos = base + 4 * (size_t)n;
+    g->t = (uint32_t)t;
+    g->ninv = found->ninv;
+    g->ninv_sh = found->ninv_sh;
+    return ZINC_OK;
+}
+
+static zinc_status batch_codec(zinc_ctx* c, uint64_t t, bool decode, const int64_t* in, uint32_t batch, int64_t* out,
+                               void* stream, const char* fn) {
+    if (!c) return fail(ZINC_E_INVAL, std::string(fn) + ": null context");
+    if (zinc_status s = check_batch(fn, batch, {in, out})) return s;
+    BatchArgs g;
+    if (zinc_status s = batch_args(c, t, &g, fn)) return s;
+    if (batch == 0) return ZINC_OK;
+    return launched(launch_batch_codec(g, c->log_n, decode, in, batch, out, (hipStream_t)stream), fn);
+}
+
+zinc_status zinc_batch_encode(zinc_ctx* c, uint64_t t, const int64_t* slots, uint32_t batch, int64_t* m,
+                              void* stream) {
+    return batch_codec(c, t, false, slots, batch, m, stream, "zinc_batch_encode");
+}
+
+zinc_status zinc_batch_decode(zinc_ctx* c, uint64_t t, const int64_t* m, uint32_t batch, int64_t* slots,
+                              void* stream) {
+    return batch_codec(c, t, true, m, batch, slots, stream, "zinc_batch_decode");
 }
 
 zinc_status zinc_elementwise_zinc(zinc_ctx* c, const uint64_t* hat, uint32_t batch, uint64_t* ct, void* stream) {

@@ -75,6 +75,15 @@ struct BfvConsts {
     uint64_t w_mod_t[ZINC_MAX_MODULI];    // floor(t Qt_l / q_l) mod t
 };
 
+// Tables of the batch (slot) encoding for a prime t = 1 mod 2N, t < 2^31
+// (kernels_batch.hip); the pointers are device memory owned by the context.
+struct BatchArgs {
+    const uint32_t* tw;      // [N][2] (zeta^brv(k), floor(zeta^brv(k) 2^32 / t))
+    const uint32_t* itw;     // [N][2] (zeta^-brv(k), companion)
+    const uint32_t* pos;     // [N]    entry of the forward transform holding slot j
+    uint32_t t, ninv, ninv_sh;
+};
+
 // Constants of BGV decoding for plaintext modulus t (kernels_bfv.hip).
 struct BgvConsts {
     uint64_t t;
@@ -127,6 +136,12 @@ struct zinc_ctx {
     uint32_t reg_epilogue = 0;    // bit s: scheme s stores from the last pass's registers
     zinc::LimbConst h_limbs[ZINC_MAX_MODULI] = {};   // host copy of the limb constants
     bool keyed = false, precomputed = false;
+    struct BatchTable {           // batch-encoding tables per plaintext modulus t
+        uint64_t t;
+        void* d;                  // device block: tw [N][2], itw [N][2], pos [N] (uint32)
+        uint32_t ninv, ninv_sh;
+    };
+    std::vector<BatchTable> batch_tables;
     // device allocations owned by the context
     void* d_block = nullptr;      // one allocation holding every table and key
     zinc::DevParams dev{};
@@ -179,6 +194,8 @@ hipError_t launch_bfv_encode(const DevParams& p, const BfvConsts& k, const int64
                              hipStream_t s);
 hipError_t launch_bfv_decode(const DevParams& p, const BfvConsts& k, const uint64_t* pt, uint32_t batch, int64_t* m,
                              hipStream_t s);
+hipError_t launch_batch_codec(const BatchArgs& g, uint32_t log_n, bool decode, const int64_t* in, uint32_t batch,
+                              int64_t* out, hipStream_t s);
 hipError_t launch_bgv_decode(const DevParams& p, const BgvConsts& k, const uint64_t* pt, uint32_t batch, int64_t* m,
                              hipStream_t s);
 

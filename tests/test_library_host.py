@@ -92,6 +92,8 @@ def test_null_arguments_are_rejected(lib):
     assert lib.zinc_bfv_encode(None, 257, None, 1, None, None) == zinc.ZINC_E_INVAL
     assert lib.zinc_bfv_decode(None, 257, None, 1, None, None) == zinc.ZINC_E_INVAL
     assert lib.zinc_set_bgv(None, 257) == zinc.ZINC_E_INVAL
+    assert lib.zinc_batch_encode(None, 65537, None, 1, None, None) == zinc.ZINC_E_INVAL
+    assert lib.zinc_batch_decode(None, 65537, None, 1, None, None) == zinc.ZINC_E_INVAL
     assert lib.zinc_bgv_encode(None, None, 1, None, None) == zinc.ZINC_E_INVAL
     assert lib.zinc_bgv_decode(None, None, 1, None, None) == zinc.ZINC_E_INVAL
     assert lib.zinc_encrypt_vanilla_sp(None, None, 1, None, None, None) == zinc.ZINC_E_INVAL

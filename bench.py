@@ -62,6 +62,21 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
+SETTLE_MS = 250.0
+
+
+def settle(fn):
+    """Run fn for about SETTLE_MS of wall time before the warmup steps: the
+    GPU's clocks rise over the first tens of milliseconds under load, and the
+    timed steps should see the clocks a sustained workload runs at."""
+    import torch
+    t0 = time.perf_counter()
+    while (time.perf_counter() - t0) * 1e3 < SETTLE_MS:
+        for _ in range(4):
+            fn()
+        torch.cuda.synchronize()
+
+
 def butterflies(n: int, limbs: int, scheme: int) -> int:
     ntts = (2 if scheme == 1 else 3) * limbs
     return ntts * (n // 2) * int(math.log2(n))
@@ -200,6 +215,7 @@ def bench_config_table(steps: int, warmup: int, budget_s: float) -> list:
         ct = torch.empty((ws.batch, 2, ps.limbs, ps.n), dtype=torch.int64, device="cuda")
         items = [(ps, zh[i]) for i in range(ws.batch)]
         for name, sch in (("zinc", 1), ("vanilla", 0)):
+            settle(lambda: ctx.encrypt_slots(sch, z, ids, ct))
             for _ in range(max(1, warmup)):
                 ctx.encrypt_slots(sch, z, ids, ct)
             torch.cuda.synchronize()
@@ -250,6 +266,7 @@ def bench_elementwise(ctx, ps, batch: int, steps: int, warmup: int) -> dict:
     out_d = {}
     for name, fn, per_ct in (("zinc", lambda: ctx.elementwise_zinc(hat, out), 32 * L * n),
                              ("vanilla", lambda: ctx.elementwise_vanilla(uhat, hat, out), 40 * L * n)):
+        settle(fn)
         for _ in range(max(1, warmup)):
             fn()
         torch.cuda.synchronize()
@@ -300,8 +317,8 @@ def bench_table2(chunk: int = 1024, reps: int = 2) -> dict:
                 for s0 in range(0, d.rows, chunk):
                     n = min(chunk, d.rows - s0)
                     ctx.encrypt_slots(sch, z[s0:s0 + n], ids[s0:s0 + n], ct[:n])
-            ctx.encrypt_slots(sch, z[:1], ids[:1], ct[:1])
-            torch.cuda.synchronize()
+            m = min(chunk, d.rows)
+            settle(lambda: ctx.encrypt_slots(sch, z[:m], ids[:m], ct[:m]))
             a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             a.record()
             for _ in range(reps):
@@ -352,6 +369,7 @@ def bench_mixed(ctxs, steps: int, warmup: int) -> dict:
            "ciphertext_gib": mb.ct_words * 8 / 2 ** 30}
     for name, sch in (("zinc", 1), ("vanilla", 0)):
         plan = zinc.Plan(ctxs, items, sch)
+        settle(lambda: plan.launch(d_slots, d_ct))
         for _ in range(max(1, warmup)):
             plan.launch(d_slots, d_ct)
         torch.cuda.synchronize()
@@ -413,10 +431,13 @@ def bench_serving(ctxs, saturated_enc_per_s: float, n_requests: int, warm: int, 
 
 
 def main():
+    global SETTLE_MS
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--settle-ms", type=float, default=SETTLE_MS,
+                    help="untimed launches before the warmup steps, in ms of wall time (clock ramp)")
     ap.add_argument("--workload", default="n8192_b1024")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -439,6 +460,7 @@ def main():
                     help="also run one torch copy of this many MiB (reference kernel for HBM byte counters)")
     args = ap.parse_args()
 
+    SETTLE_MS = args.settle_ms
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}); "
               "ciphertexts are independent, so N GPUs would each run this benchmark on 1/N of the batch.",
@@ -476,6 +498,7 @@ def main():
     res = {}
     for name in run:
         sch = schemes[name]
+        settle(lambda: ctx.encrypt_slots(sch, z, ids, ct))
         for _ in range(args.warmup):
             ctx.encrypt_slots(sch, z, ids, ct)
         torch.cuda.synchronize()

@@ -19,6 +19,9 @@ namespace {
 // than this fraction, so that near-ties resolve the same way run after run.
 constexpr double kMinGain = 0.01;
 
+// Kernel time (ms) spent before the first timed candidate (Bench::settle).
+constexpr double kSettleMs = 200.0;
+
 // Forms of the fused kernel: (coefficients per thread, register epilogue).
 bool form_ok(uint32_t log_n, uint32_t tile, bool reg) {
     if (log_n == 15) return tile == 16 && !reg;
@@ -127,6 +130,23 @@ struct Bench {
         std::sort(ms.begin(), ms.end());
         return ms[ms.size() / 2];
     }
+
+    // The GPU's clocks rise over the first tens of milliseconds under load:
+    // run `scheme` until about `target_ms` of kernel time has passed, so that
+    // the first candidates are not timed at lower clocks than the last.
+    bool settle(int scheme, double target_ms) {
+        double done = 0;
+        for (int round = 0; round < 4096 && done < target_ms; ++round) {
+            if (hipEventRecord(a, s) != hipSuccess) return false;
+            for (int i = 0; i < 4; ++i)
+                if (zinc_encrypt_slots(c, scheme, slots, c->n / 2, batch, ids, ct, s) != ZINC_OK) return false;
+            if (hipEventRecord(b, s) != hipSuccess || hipEventSynchronize(b) != hipSuccess) return false;
+            float t = 0;
+            if (hipEventElapsedTime(&t, a, b) != hipSuccess) return false;
+            done += t;
+        }
+        return true;
+    }
 };
 
 }  // namespace
@@ -221,6 +241,8 @@ zinc_status zinc_autotune(zinc_ctx* c, uint32_t batch, const char* cache_path, z
     double best_total = -1;
     zinc_tuning best{{saved_tile[0], saved_tile[1]}, default_mask, saved_reg};
     if (e != hipSuccess) st = plan_fail(ZINC_E_HIP, std::string("zinc_autotune: setup: ") + hipGetErrorString(e));
+    if (st == ZINC_OK && !bn.settle(0, kSettleMs))
+        st = plan_fail(ZINC_E_HIP, "zinc_autotune: warm-up launch failed");
     for (size_t mi = 0; st == ZINC_OK && mi < masks.size(); ++mi) {
         st = apply_arith(c, masks[mi]);
         double total = 0;

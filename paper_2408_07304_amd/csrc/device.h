@@ -202,7 +202,7 @@ __device__ __forceinline__ uint32_t opaque_s(uint32_t x) {   // x must be wave-u
 // indices drop every index bit below the butterfly's bit, so when the pass's
 // active bits lie above the 64 lane bits (LO >= 6) the twiddles are uniform
 // across the wavefront: the index is then taken from the first lane, which puts
-// it in scalar registers and turns the twiddle loads into scalar loads.
+// it in scalar registers (and, with uniform_tw, the loads on the scalar path).
 template <class G, int P>
 __device__ __forceinline__ uint32_t tw_tpart(uint32_t t) {
     constexpr int LO = G::LO(P), HH = G::H(P);
@@ -248,6 +248,27 @@ typedef double f64x2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ u64x2 load_pair(const u64* p) { return *reinterpret_cast<const u64x2*>(p); }
 __device__ __forceinline__ f64x2 load_pair(const double* p) { return *reinterpret_cast<const f64x2*>(p); }
 
+// Passes whose twiddle index is the same in every lane (see tw_tpart).  With
+// 16 or more coefficients per thread their twiddles are read through the
+// constant address space (the tables are never written while a kernel runs),
+// which lets the compiler use scalar loads and keeps them off the vector
+// memory path (vanilla at N = 8192: 2 % faster).  With 8 per thread the
+// scalar loads, which share a wait counter with the LDS exchanges, measured
+// slightly slower, so those geometries keep vector loads.
+template <class G, int P>
+__device__ __forceinline__ constexpr bool uniform_tw() { return G::R >= 16 && (P == 0 || G::LO(P) >= 6); }
+__device__ __forceinline__ u64x2 load_pair_uniform(const u64* p) {
+    return *(const __attribute__((address_space(4))) u64x2*)(p);
+}
+__device__ __forceinline__ f64x2 load_pair_uniform(const double* p) {
+    return *(const __attribute__((address_space(4))) f64x2*)(p);
+}
+template <class G, int P, class T>
+__device__ __forceinline__ auto load_tw(const T* p) {
+    if constexpr (uniform_tw<G, P>()) return load_pair_uniform(p);
+    else return load_pair(p);
+}
+
 // ---- integer path (any modulus below 2^60): Shoup butterflies, [0, 4q) ----
 
 template <class G, int P>
@@ -262,7 +283,7 @@ __device__ __forceinline__ void fwd_pass(u64 (&v)[G::R], uint32_t t, const u64* 
         for (int c = 0; c < G::R; ++c) {
             if (c & (1 << b)) continue;
             const uint32_t ti = toff + 2 * tw_index<G, P>(tp, c, b, smul);
-            const u64x2 w = load_pair(tw + ti);
+            const u64x2 w = load_tw<G, P>(tw + ti);
             ct_bfly(v[c], v[c | (1 << b)], w.x, w.y, q, q2);
         }
     }
@@ -279,7 +300,7 @@ __device__ __forceinline__ void inv_pass(u64 (&v)[G::R], uint32_t t, const u64* 
         for (int c = 0; c < G::R; ++c) {
             if (c & (1 << b)) continue;
             const uint32_t ti = toff + 2 * tw_index<G, P>(tp, c, b, smul);
-            const u64x2 w = load_pair(itw + ti);
+            const u64x2 w = load_tw<G, P>(itw + ti);
             gs_bfly(v[c], v[c | (1 << b)], w.x, w.y, q, q2);
         }
     }
@@ -411,7 +432,7 @@ __device__ __forceinline__ void fwd_pass_fp(double (&v)[G::R], uint32_t t, const
         for (int c = 0; c < G::R; ++c) {
             if (c & (1 << b)) continue;
             const uint32_t ti = toff + 2 * tw_index<G, P>(tp, c, b, smul);
-            const f64x2 w = load_pair(tw + ti);
+            const f64x2 w = load_tw<G, P>(tw + ti);
             ct_bfly_fp(v[c], v[c | (1 << b)], w.x, w.y, q);
         }
     }

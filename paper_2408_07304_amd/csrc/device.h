@@ -36,6 +36,14 @@ __device__ __forceinline__ u64 reduce_signed(long long x, const LimbConst& lc) {
     return (x < 0 && r != 0) ? lc.q - r : r;
 }
 
+// reduce_signed with a cheap path for |x| < q (q < 2^62), the usual size of
+// an encoded message coefficient plus noise
+__device__ __forceinline__ u64 reduce_signed_near(long long x, const LimbConst& lc) {
+    const long long q = (long long)lc.q;
+    if (x > -q && x < q) return (u64)(x < 0 ? x + q : x);
+    return reduce_signed(x, lc);
+}
+
 // residue of a small signed integer (|x| < q)
 __device__ __forceinline__ u64 small_mod(int x, u64 q) {
     return x < 0 ? q - (u64)(unsigned)(-x) : (u64)(unsigned)x;
@@ -94,12 +102,12 @@ __device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint
                                      uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
-        const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
-        c0 = hi1 ^ c1 ^ k0;
-        c1 = lo1;
-        c2 = hi0 ^ c3 ^ k1;
-        c3 = lo0;
+        // one 32 x 32 -> 64-bit product each (a single v_mad_u64_u32)
+        const u64 p0 = (u64)0xD2511F53u * c0, p1 = (u64)0xCD9E8D57u * c2;
+        c0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        c1 = (uint32_t)p1;
+        c2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c3 = (uint32_t)p0;
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }
@@ -640,11 +648,17 @@ __device__ __forceinline__ void encode_p0(long long (&m)[G::R], u64* lds, const 
         const C2 w = cmul(A[padc(i)], C2{p.twist[2 * i], p.twist[2 * i + 1]});
         double x = (idx < (uint32_t)H ? w.x : w.y) * f;
         x = __builtin_rint(x);
-        if (!(__builtin_fabs(x) < 4611686018427387904.0)) {   // 2^62 (also catches NaN)
-            bad = true;
-            x = 0.0;
+        if (__builtin_fabs(x) < 0x1p51) {
+            // an integer below 2^51: adding 1.5 * 2^52 is exact and leaves it
+            // in the low mantissa bits, read off with one 64-bit subtraction
+            m[c] = __double_as_longlong(x + 0x1.8p52) - 0x4338000000000000ll;
+        } else {
+            if (!(__builtin_fabs(x) < 4611686018427387904.0)) {   // 2^62 (also catches NaN)
+                bad = true;
+                x = 0.0;
+            }
+            m[c] = (long long)x;
         }
-        m[c] = (long long)x;
     }
     if (bad) atomicOr(p.err, 1u);
 }

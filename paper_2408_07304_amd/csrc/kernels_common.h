@@ -172,7 +172,7 @@ struct MessageIn {
     static_assert(!(FROM_SLOTS && BGV), "BGV encrypts integer plaintexts");
     __device__ __forceinline__ u64 ri(int c) const {       // residue in [0, 2q)
         const uint32_t k = tp0 | G::cpart(0, c);
-        if constexpr (FROM_SLOTS) return reduce_signed(stash[k] + e.get(c), lc);
+        if constexpr (FROM_SLOTS) return reduce_signed_near(stash[k] + e.get(c), lc);
         else return pt[k] + noise_ri<BGV>(e.get(c), noise_t, lc);
     }
     __device__ __forceinline__ double rf(int c) const {    // |value| <= q

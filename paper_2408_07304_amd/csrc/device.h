@@ -24,9 +24,6 @@ __device__ __forceinline__ u64 shoup_lazy(u64 y, u64 w, u64 wp, u64 q) {
 
 __device__ __forceinline__ u64 csub(u64 x, u64 m) { return x >= m ? x - m : x; }
 
-// [0, 4q) -> [0, q)
-__device__ __forceinline__ u64 canon4(u64 x, u64 q, u64 q2) { return csub(csub(x, q2), q); }
-
 __device__ __forceinline__ u64 addmod(u64 a, u64 b, u64 q) { return csub(a + b, q); }
 
 // residue of a signed 64-bit integer with |x| < 2^63
@@ -49,13 +46,28 @@ __device__ __forceinline__ u64 small_mod(int x, u64 q) {
     return x < 0 ? q - (u64)(unsigned)(-x) : (u64)(unsigned)x;
 }
 
-// Cooley-Tukey butterfly with Harvey's lazy reduction: x, y in [0, 4q) ->
-// (x + y w, x - y w) in [0, 4q).
-__device__ __forceinline__ void ct_bfly(u64& x, u64& y, u64 w, u64 wp, u64 q, u64 q2) {
-    const u64 a = csub(x, q2);
+// Cooley-Tukey butterfly with lazy reduction (moduli below 2^60, so 16 q fits
+// in 64 bits): the Shoup product t = y w mod q lies in [0, 2q) for any 64-bit
+// y, so (a + t, a - t + 2q) exceed the bound of a by at most 2q.  RED: first
+// bring x from [0, 16q) into [0, 8q); otherwise a = x.  ntt_fwd places the
+// reductions so that no value reaches 16q (see fwd_reduce).
+template <bool RED>
+__device__ __forceinline__ void ct_bfly(u64& x, u64& y, u64 w, u64 wp, u64 q, u64 q2, u64 q8) {
+    const u64 a = RED ? csub(x, q8) : x;
     const u64 t = shoup_lazy(y, w, wp, q);
     x = a + t;
     y = a - t + q2;
+}
+
+// Stage j (0-based) of an integer forward transform whose inputs lie in
+// [0, 4q): without reductions the bound after j stages is (4 + 2j) q, so the
+// first reduction is due at stage 6 (bound 16q) and then every fourth stage
+// (8q + 4 * 2q).  Outputs lie in [0, 16q).
+__host__ __device__ constexpr bool fwd_reduce(int j) { return j >= 6 && (j - 6) % 4 == 0; }
+
+// [0, 16q) -> [0, q)
+__device__ __forceinline__ u64 canon16(u64 x, u64 q) {
+    return csub(csub(csub(csub(x, q << 3), q << 2), q << 1), q);
 }
 
 // Gentleman-Sande butterfly: x, y in [0, 2q) -> (x + y, (x - y) w) in [0, 2q).
@@ -284,15 +296,18 @@ __device__ __forceinline__ void fwd_pass(u64 (&v)[G::R], uint32_t t, const u64* 
                                          uint32_t toff, uint32_t smul, u64 q, u64 q2) {
     constexpr int K = G::K(P);
     const uint32_t tp = tw_tpart<G, P>(t);
+    const u64 q8 = q << 3;
 #pragma unroll
     for (int i = 0; i < K; ++i) {
         const int b = K - 1 - i;
+        constexpr int J0 = G::LOGN - G::H(P);            // stages before this pass
 #pragma unroll
         for (int c = 0; c < G::R; ++c) {
             if (c & (1 << b)) continue;
             const uint32_t ti = toff + 2 * tw_index<G, P>(tp, c, b, smul);
             const u64x2 w = load_tw<G, P>(tw + ti);
-            ct_bfly(v[c], v[c | (1 << b)], w.x, w.y, q, q2);
+            if (fwd_reduce(J0 + i)) ct_bfly<true>(v[c], v[c | (1 << b)], w.x, w.y, q, q2, q8);
+            else ct_bfly<false>(v[c], v[c | (1 << b)], w.x, w.y, q, q2, q8);
         }
     }
 }
@@ -328,7 +343,7 @@ __device__ __forceinline__ void fwd_rest(u64 (&v)[G::R], u64* lds, const u64* __
 }
 
 // Forward NTT modulo q of limb `limb`: v in pass-0 layout with values in
-// [0, 4q) -> v in the last pass's layout with values in [0, 4q).  tw is the
+// [0, 4q) -> v in the last pass's layout with values in [0, 16q) (canon16).  tw is the
 // [M][NT][2] table of (psi^brv(k), Shoup companion) of NT-point transforms
 // (NT = G::N, or 2 G::N for a half of a split transform, smul = 2 + half);
 // lds the padded exchange buffer.

@@ -58,7 +58,7 @@ __global__ void __launch_bounds__(Cfg<LOGN>::G::T) k_keygen(DevParams p, u64* sk
 #pragma unroll
     for (int i = 0; i < R; ++i) {
         const uint32_t k = t + G::T * i;
-        sh[i] = canon4(lds[pad(k)], q, q2);
+        sh[i] = canon16(lds[pad(k)], q);
         shs[i] = shoup_companion_dev(sh[i], q);
         sk[(size_t)l * N + k] = sh[i];
         sk_sh[(size_t)l * N + k] = shs[i];
@@ -72,7 +72,7 @@ __global__ void __launch_bounds__(Cfg<LOGN>::G::T) k_keygen(DevParams p, u64* sk
 #pragma unroll
     for (int i = 0; i < R; ++i) {
         const uint32_t k = t + G::T * i;
-        const u64 eh = canon4(lds[pad(k)], q, q2);
+        const u64 eh = canon16(lds[pad(k)], q);
         // a <- R_q, drawn directly in the NTT domain: 128 uniform bits mod q
         const U4 r = draw(p.seed, ZINC_KEY_ID, TAG_A, l, k);
         const u64 hi = ((u64)r.w << 32) | r.z, lo = ((u64)r.y << 32) | r.x;

@@ -83,14 +83,14 @@ struct LimbNtt {
             for (int c = 0; c < G::R; ++c) v[c] = in_int(c);
             ntt_fwd<G>(v, lds, tw, limb, q, q2, t);
 #pragma unroll
-            for (int c = 0; c < G::R; ++c) res[c] = canon4(v[c], q, q2);
+            for (int c = 0; c < G::R; ++c) res[c] = canon16(v[c], q);
         }
     }
 
     // canonical residue of transform coefficient k (after run())
     __device__ __forceinline__ u64 canon(uint32_t k) const {
         if (fp()) return fp_canon(reinterpret_cast<const double*>(lds)[pad(k)], qd, qinv);
-        return canon4(lds[pad(k)], q, q2);
+        return canon16(lds[pad(k)], q);
     }
 
     // a * b mod q for canonical residues a, b (the pk * u_hat product)

@@ -159,7 +159,7 @@ struct SplitLimb {
 
     __device__ __forceinline__ u64 canon(uint32_t k) const {
         if (fp()) return fp_canon(reinterpret_cast<const double*>(lds)[pad(k)], qd, qinv);
-        return canon4(lds[pad(k)], q, q2);
+        return canon16(lds[pad(k)], q);
     }
 
     __device__ __forceinline__ u64 mul(u64 a, u64 b, u64 b_sh) const {

@@ -426,10 +426,11 @@ __device__ __forceinline__ double fp_round_reduce(double x, double q, double qin
 }
 
 // exact integer in (-2^52, 2^52) -> canonical residue in [0, q) as uint64
+// (x * qinv is within 1.01/q of x/q, so the rounded quotient leaves |r| <=
+// q/2 + 1, and one correction of the negative side gives [0, q).)
 __device__ __forceinline__ u64 fp_canon(double x, double q, double qinv) {
-    double r = __builtin_fma(-__builtin_floor(x * qinv), q, x);   // [-q, 2q)
+    double r = __builtin_fma(-__builtin_rint(x * qinv), q, x);
     r = r < 0.0 ? r + q : r;
-    r = r >= q ? r - q : r;
     return (u64)__double_as_longlong(r + 0x1p52) - 0x4330000000000000ull;
 }
 
@@ -592,88 +593,114 @@ __device__ __forceinline__ void fft_dit(C2* A, const double* __restrict__ fft_tw
 // them back to the same places, so one barrier per pass suffices.  Every
 // butterfly performs the operations of fft_dit on the same values, so the
 // result equals fft_dit's bit for bit, for any T.  A is indexed through padc().
+// PARTIAL: the workgroup has more than T threads; all of them reach the
+// barriers and only threads t < T work.
 __host__ __device__ constexpr uint32_t padc(uint32_t i) { return i + (i >> 4); }
 __host__ __device__ constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x >> 1); }
 
-template <int LOGH, int LOGT, int SIGN, int LOGTAB, int P>
+template <int LOGH, int LOGT, int SIGN, int LOGTAB, int P, bool PARTIAL>
 __device__ __forceinline__ void fft_reg_pass(C2* A, const double* __restrict__ fft_tw, uint32_t t) {
     constexpr int LOGR = LOGH - LOGT, R = 1 << LOGR;
     constexpr int B = P * LOGR, K = (LOGH - B < LOGR) ? LOGH - B : LOGR;
     if constexpr (B < LOGH) {
-        uint32_t idx[R];
-        C2 v[R];
-#pragma unroll
-        for (int e = 0; e < R; ++e) {
-            const uint32_t c = (uint32_t)e & ((1u << K) - 1u), rest = t | ((uint32_t)(e >> K) << LOGT);
-            idx[e] = (rest & ((1u << B) - 1u)) | (c << B) | ((rest >> B) << (B + K));
-            v[e] = A[padc(idx[e])];
-        }
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const int s = B + k + 1;
-            const uint32_t half = 1u << (s - 1);
+        if (!PARTIAL || t < (1u << LOGT)) {
+            uint32_t idx[R];
+            C2 v[R];
 #pragma unroll
             for (int e = 0; e < R; ++e) {
-                if (e & (1 << k)) continue;
-                const uint32_t ti = (idx[e] & (half - 1u)) << (LOGTAB - s);
-                C2 w{fft_tw[2 * ti], fft_tw[2 * ti + 1]};
-                if (SIGN > 0) w.y = -w.y;
-                const C2 a = v[e], bw = cmul(v[e | (1 << k)], w);
-                v[e] = C2{a.x + bw.x, a.y + bw.y};
-                v[e | (1 << k)] = C2{a.x - bw.x, a.y - bw.y};
+                const uint32_t c = (uint32_t)e & ((1u << K) - 1u), rest = t | ((uint32_t)(e >> K) << LOGT);
+                idx[e] = (rest & ((1u << B) - 1u)) | (c << B) | ((rest >> B) << (B + K));
+                v[e] = A[padc(idx[e])];
             }
-        }
 #pragma unroll
-        for (int e = 0; e < R; ++e) A[padc(idx[e])] = v[e];
+            for (int k = 0; k < K; ++k) {
+                const int s = B + k + 1;
+                const uint32_t half = 1u << (s - 1);
+#pragma unroll
+                for (int e = 0; e < R; ++e) {
+                    if (e & (1 << k)) continue;
+                    const uint32_t ti = (idx[e] & (half - 1u)) << (LOGTAB - s);
+                    C2 w{fft_tw[2 * ti], fft_tw[2 * ti + 1]};
+                    if (SIGN > 0) w.y = -w.y;
+                    const C2 a = v[e], bw = cmul(v[e | (1 << k)], w);
+                    v[e] = C2{a.x + bw.x, a.y + bw.y};
+                    v[e | (1 << k)] = C2{a.x - bw.x, a.y - bw.y};
+                }
+            }
+#pragma unroll
+            for (int e = 0; e < R; ++e) A[padc(idx[e])] = v[e];
+        }
         __syncthreads();
-        fft_reg_pass<LOGH, LOGT, SIGN, LOGTAB, P + 1>(A, fft_tw, t);
+        fft_reg_pass<LOGH, LOGT, SIGN, LOGTAB, P + 1, PARTIAL>(A, fft_tw, t);
     }
 }
 
-template <int LOGH, int T, int SIGN, int LOGTAB = LOGH>
+template <int LOGH, int T, int SIGN, int LOGTAB = LOGH, bool PARTIAL = false>
 __device__ __forceinline__ void fft_dit_reg(C2* A, const double* __restrict__ fft_tw, uint32_t t) {
     static_assert((1 << ilog2(T)) == T && ilog2(T) < LOGH, "T must be a power of two below 2^LOGH");
-    fft_reg_pass<LOGH, ilog2(T), SIGN, LOGTAB, 0>(A, fft_tw, t);
+    fft_reg_pass<LOGH, ilog2(T), SIGN, LOGTAB, 0, PARTIAL>(A, fft_tw, t);
 }
 
 // CKKS encoding of one slot vector into the integer coefficients m held in
-// pass-0 layout: place Delta z_j at position (5^j mod 2N - 1)/4 of an N/2-point
-// vector, transform, twist by zeta^-i and scale by 2/N; coefficient i < N/2 is
-// the real part of entry i, coefficient i + N/2 its imaginary part; round half
-// to even.  Uses lds (LdsWords<N> words) as the padded complex work array.
+// pass-0 layout: place Delta z_j at position (5^j mod 2N - 1)/4 of a real
+// N/2-point vector Z, transform, twist by zeta^-i and scale by 2/N;
+// coefficient i < N/2 is the real part of entry i, coefficient i + N/2 its
+// imaginary part; round half to even.  Z is real, so the transform runs on
+// Y[k] = Z[2k] + i Z[2k+1] (Q = N/4 points) and is unscrambled: with Yf its
+// transform, E[m] = (Yf[m] + conj Yf[Q-m]) / 2, O[m] = (Yf[m] - conj Yf[Q-m]) / 2i
+// and F[m] = E[m mod Q] + exp(-2 pi i m / (N/2)) O[m mod Q].  The Q-point
+// transform runs on Q/8 threads (8 points each, fewer passes); the others wait
+// at its barriers.  A thread's registers c and c | TOP hold coefficients i and
+// i + N/2, which come from the same entry F[i].  Uses lds (LdsWords<N> words)
+// as the padded complex work array.
 template <class G>
 __device__ __forceinline__ void encode_p0(long long (&m)[G::R], u64* lds, const DevParams& p,
                                           const double* __restrict__ z, uint32_t n_slots, uint32_t t) {
-    constexpr int H = G::N / 2, LOGH = G::LOGN - 1;
+    constexpr int H = G::N / 2, Q = H / 2, LOGH = G::LOGN - 1, LOGQ = LOGH - 1;
+    constexpr int TF = Q / 8 < G::T ? Q / 8 : G::T;
+    double* Ad = reinterpret_cast<double*>(lds);
     C2* A = reinterpret_cast<C2*>(lds);
     __syncthreads();
     for (uint32_t j = t; j < (uint32_t)H; j += G::T) {
         const double val = j < n_slots ? p.scale * z[j] : 0.0;
-        A[padc(p.slot_pos[j])] = C2{val, 0.0};
+        const uint32_t bk = p.slot_pos[j];               // brv_{log H}(k_j)
+        Ad[2 * padc(bk & (Q - 1)) + (bk >> (LOGH - 1))] = val;   // Y[k_j / 2] gets Z[k_j] in Re or Im
     }
     __syncthreads();
-    fft_dit_reg<LOGH, G::T, -1>(A, p.fft_tw, t);
+    fft_dit_reg<LOGQ, TF, -1, LOGH, (TF < G::T)>(A, p.fft_tw, t);
     const double f = 2.0 / (double)G::N;
+    constexpr int TOP = 1 << (G::K(0) - 1);
     const uint32_t tp = G::tpart(0, t);
     bool bad = false;
+    auto to_int = [&](double x) -> long long {
+        x = __builtin_rint(x);
+        // an integer below 2^51: adding 1.5 * 2^52 is exact and leaves it in
+        // the low mantissa bits, read off with one 64-bit subtraction
+        if (__builtin_fabs(x) < 0x1p51) return __double_as_longlong(x + 0x1.8p52) - 0x4338000000000000ll;
+        if (!(__builtin_fabs(x) < 4611686018427387904.0)) {   // 2^62 (also catches NaN)
+            bad = true;
+            return 0;
+        }
+        return (long long)x;
+    };
 #pragma unroll
     for (int c = 0; c < G::R; ++c) {
-        const uint32_t idx = tp | G::cpart(0, c);
-        const uint32_t i = idx & (H - 1);
-        const C2 w = cmul(A[padc(i)], C2{p.twist[2 * i], p.twist[2 * i + 1]});
-        double x = (idx < (uint32_t)H ? w.x : w.y) * f;
-        x = __builtin_rint(x);
-        if (__builtin_fabs(x) < 0x1p51) {
-            // an integer below 2^51: adding 1.5 * 2^52 is exact and leaves it
-            // in the low mantissa bits, read off with one 64-bit subtraction
-            m[c] = __double_as_longlong(x + 0x1.8p52) - 0x4338000000000000ll;
-        } else {
-            if (!(__builtin_fabs(x) < 4611686018427387904.0)) {   // 2^62 (also catches NaN)
-                bad = true;
-                x = 0.0;
-            }
-            m[c] = (long long)x;
+        if (c & TOP) continue;
+        const uint32_t i = tp | G::cpart(0, c);         // < H
+        const uint32_t m1 = i & (Q - 1), m2 = (Q - m1) & (Q - 1);
+        const C2 y1 = A[padc(m1)], y2 = A[padc(m2)];
+        const C2 ev{0.5 * (y1.x + y2.x), 0.5 * (y1.y - y2.y)};     // (Y1 + conj Y2) / 2
+        const C2 od{0.5 * (y1.y + y2.y), -0.5 * (y1.x - y2.x)};    // (Y1 - conj Y2) / 2i
+        C2 w{p.fft_tw[2 * (i & (H / 2 - 1))], p.fft_tw[2 * (i & (H / 2 - 1)) + 1]};
+        if (i >= (uint32_t)(H / 2)) {
+            w.x = -w.x;
+            w.y = -w.y;
         }
+        const C2 o = cmul(w, od);
+        const C2 F{ev.x + o.x, ev.y + o.y};
+        const C2 r = cmul(F, C2{p.twist[2 * i], p.twist[2 * i + 1]});
+        m[c] = to_int(r.x * f);
+        m[c | TOP] = to_int(r.y * f);
     }
     if (bad) atomicOr(p.err, 1u);
 }

@@ -432,8 +432,9 @@ zinc_status zinc_get_tuning(const zinc_ctx* ctx, zinc_tuning* t);
 /* Time every combination of forms and arithmetic on `batch` (1..65536)
  * plaintexts of N/2 slots uniform on [-1, 1) (a fixed pseudo-random sequence)
  * with zinc_encrypt_slots (vanilla, and Zinc when
- * precomputed), on a private stream with HIP events (median of 5 runs after
- * 2 warm-up runs), and keep the fastest; candidates are tried default form
+ * precomputed), on a private stream with HIP events (after 200 ms of
+ * untimed launches; each candidate's best, over two sweeps, median of 9 runs
+ * after 2 warm-up runs), and keep the fastest; candidates are tried default form
  * first, and a later one is kept only if more than 1% faster, so that
  * near-ties resolve the same way each time.  cache_path (may be NULL) names a
  * text file of earlier results keyed by device architecture, CU count, ring

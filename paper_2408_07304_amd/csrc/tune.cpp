@@ -19,8 +19,10 @@ namespace {
 // than this fraction, so that near-ties resolve the same way run after run.
 constexpr double kMinGain = 0.01;
 
-// Kernel time (ms) spent before the first timed candidate (Bench::settle).
+// Kernel time (ms) spent before the first timed candidate (Bench::settle),
+// and the number of sweeps over the candidates.
 constexpr double kSettleMs = 200.0;
+constexpr int kRounds = 2;
 
 // Forms of the fused kernel: (coefficients per thread, register epilogue).
 bool form_ok(uint32_t log_n, uint32_t tile, bool reg) {
@@ -117,7 +119,7 @@ struct Bench {
 
     // Median time of one batch in ms, or a negative value on failure.
     double time(int scheme) {
-        constexpr int kWarm = 2, kRuns = 5;
+        constexpr int kWarm = 2, kRuns = 9;
         std::vector<double> ms;
         for (int i = 0; i < kWarm + kRuns; ++i) {
             if (hipEventRecord(a, s) != hipSuccess) return -1;
@@ -243,34 +245,51 @@ zinc_status zinc_autotune(zinc_ctx* c, uint32_t batch, const char* cache_path, z
     if (e != hipSuccess) st = plan_fail(ZINC_E_HIP, std::string("zinc_autotune: setup: ") + hipGetErrorString(e));
     if (st == ZINC_OK && !bn.settle(0, kSettleMs))
         st = plan_fail(ZINC_E_HIP, "zinc_autotune: warm-up launch failed");
+    // Every candidate is timed in each of kRounds sweeps and keeps its best
+    // median, so that a slow moment of the GPU does not decide the choice.
+    const size_t nf = forms.size();
+    std::vector<double> ms((size_t)masks.size() * 2 * nf, -1.0);
+    auto at = [&](size_t mi, int sc, size_t fi) -> double& { return ms[(mi * 2 + (size_t)sc) * nf + fi]; };
+    for (int round = 0; st == ZINC_OK && round < kRounds; ++round) {
+        for (size_t mi = 0; st == ZINC_OK && mi < masks.size(); ++mi) {
+            st = apply_arith(c, masks[mi]);
+            for (int sc = 0; st == ZINC_OK && sc < n_schemes; ++sc) {
+                for (size_t fi = 0; fi < nf; ++fi) {
+                    c->tile[sc] = forms[fi].tile;
+                    c->reg_epilogue = (c->reg_epilogue & ~(1u << sc)) | ((forms[fi].reg ? 1u : 0u) << sc);
+                    const double t = bn.time(sc);
+                    ++out->n_timed;
+                    if (t < 0) {
+                        st = plan_fail(ZINC_E_HIP, "zinc_autotune: timed launch failed");
+                        break;
+                    }
+                    double& m = at(mi, sc, fi);
+                    if (m < 0 || t < m) m = t;
+                }
+            }
+        }
+    }
     for (size_t mi = 0; st == ZINC_OK && mi < masks.size(); ++mi) {
-        st = apply_arith(c, masks[mi]);
         double total = 0;
         Form pick[2] = {{16u, false}, {16u, false}};
         double pick_ms[2] = {0, 0};
-        for (int sc = 0; st == ZINC_OK && sc < n_schemes; ++sc) {
+        for (int sc = 0; sc < n_schemes; ++sc) {
             double bm = -1;
-            for (const Form& f : forms) {
-                c->tile[sc] = f.tile;
-                c->reg_epilogue = (c->reg_epilogue & ~(1u << sc)) | ((f.reg ? 1u : 0u) << sc);
-                const double ms = bn.time(sc);
-                ++out->n_timed;
-                if (ms < 0) {
-                    st = plan_fail(ZINC_E_HIP, "zinc_autotune: timed launch failed");
-                    break;
-                }
-                if (mi == 0 && f.tile == 16 && !f.reg) out->default_ms[sc] = ms;
+            for (size_t fi = 0; fi < nf; ++fi) {
+                const Form& f = forms[fi];
+                const double t = at(mi, sc, fi);
+                if (mi == 0 && f.tile == 16 && !f.reg) out->default_ms[sc] = t;
                 // candidates come in order of preference (default form first);
                 // a later one must be faster by more than the timing noise
-                if (bm < 0 || ms < bm * (1.0 - kMinGain)) {
-                    bm = ms;
+                if (bm < 0 || t < bm * (1.0 - kMinGain)) {
+                    bm = t;
                     pick[sc] = f;
                 }
             }
             pick_ms[sc] = bm;
             total += bm;
         }
-        if (st == ZINC_OK && (best_total < 0 || total < best_total * (1.0 - kMinGain))) {
+        if (best_total < 0 || total < best_total * (1.0 - kMinGain)) {
             best_total = total;
             const uint32_t reg = (pick[0].reg ? 1u : 0u) |
                                  (n_schemes == 2 ? (pick[1].reg ? 2u : 0u) : (saved_reg & 2u));

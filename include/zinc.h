@@ -42,8 +42,10 @@
  * read by zinc_device_errors.
  *
  * Threads: a context is read-only after zinc_precompute; encryption calls on
- * one context may run concurrently on different streams.  zinc_keygen and
- * zinc_precompute need exclusive use of the context.
+ * one context may run concurrently on different streams (the batch codec's
+ * first call for a plaintext modulus builds its tables under a lock).
+ * zinc_keygen, zinc_precompute, zinc_set_bgv, zinc_set_tuning and
+ * zinc_autotune need exclusive use of the context.
  *
  * Every call returns a zinc_status; zinc_last_error() gives a message for the
  * calling thread's most recent failure.

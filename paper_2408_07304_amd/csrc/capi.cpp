@@ -498,6 +498,7 @@ static zinc_status batch_args(zinc_ctx* c, uint64_t t, BatchArgs* g, const char*
     const uint32_t n = c->n, log_n = c->log_n;
     if (t < 3 || t >= (1ull << 31) || t % (2ull * n) != 1 || !is_prime(t))
         return fail(ZINC_E_INVAL, std::string(fn) + ": t must be a prime below 2^31 with t = 1 mod 2N");
+    std::lock_guard<std::mutex> lock(c->batch_mu);
     const zinc_ctx::BatchTable* found = nullptr;
     for (const auto& b : c->batch_tables)
         if (b.t == t) found = &b;

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -142,6 +143,7 @@ struct zinc_ctx {
         uint32_t ninv, ninv_sh;
     };
     std::vector<BatchTable> batch_tables;
+    std::mutex batch_mu;          // guards batch_tables (first use of a t may come from any thread)
     // device allocations owned by the context
     void* d_block = nullptr;      // one allocation holding every table and key
     zinc::DevParams dev{};

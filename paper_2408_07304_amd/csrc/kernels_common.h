@@ -116,6 +116,12 @@ __device__ __forceinline__ uint32_t out_index(uint32_t t, int c) {
 __device__ __forceinline__ void store_pair(u64* p, u64 a, u64 b) {
     *reinterpret_cast<u64x2*>(p) = u64x2{a, b};
 }
+// Final ciphertext words, which no later step of the launch reads: written
+// non-temporally so that they stream to HBM instead of displacing the
+// twiddles, keys and cached Enc(0) in L2.
+__device__ __forceinline__ void store_pair_final(u64* p, u64 a, u64 b) {
+    __builtin_nontemporal_store(u64x2{a, b}, reinterpret_cast<u64x2*>(p));
+}
 
 // Transform one polynomial of a limb and hand every coefficient pair the
 // thread owns to epi(k, v_k, v_k+1) (k even, canonical values).  REG = false:
@@ -239,7 +245,7 @@ __device__ __forceinline__ void encrypt_item_g(const DevParams& p, const double*
             transform_store<REG_EPI>(nt, t, [&](int c) { return msg.ri(c); }, [&](int c) { return msg.rf(c); },
                                      [&](uint32_t k, u64 a, u64 b) {
                                          const u64x2 z = load_pair(z1 + k);
-                                         store_pair(c1 + k, addmod(a, z.x, lc.q), addmod(b, z.y, lc.q));
+                                         store_pair_final(c1 + k, addmod(a, z.x, lc.q), addmod(b, z.y, lc.q));
                                      });
             // c2 = zero2 + NTT(e2')
             const Packed8<R> e2l = e2.fresh();
@@ -249,7 +255,7 @@ __device__ __forceinline__ void encrypt_item_g(const DevParams& p, const double*
                                      [&](int c) { return noise_rf<BGV>(e2l.get(c), p.noise_t, lc); },
                                      [&](uint32_t k, u64 a, u64 b) {
                                          const u64x2 z = load_pair(z2 + k);
-                                         store_pair(c2 + k, addmod(a, z.x, lc.q), addmod(b, z.y, lc.q));
+                                         store_pair_final(c2 + k, addmod(a, z.x, lc.q), addmod(b, z.y, lc.q));
                                      });
         }
     } else {
@@ -278,8 +284,8 @@ __device__ __forceinline__ void encrypt_item_g(const DevParams& p, const double*
                                      [&](uint32_t k, u64 a, u64 b) {
                                          const u64x2 u2 = load_pair(c2 + k), w = load_pair(pk1 + k),
                                                      ws = load_pair(pk1s + k);
-                                         store_pair(c1 + k, addmod(a, nt.mul(u2.x, w.x, ws.x), lc.q),
-                                                    addmod(b, nt.mul(u2.y, w.y, ws.y), lc.q));
+                                         store_pair_final(c1 + k, addmod(a, nt.mul(u2.x, w.x, ws.x), lc.q),
+                                                          addmod(b, nt.mul(u2.y, w.y, ws.y), lc.q));
                                      });
             // c2 = pk2 u_hat + NTT(e2)
             const Packed8<R> e2l = e2.fresh();
@@ -290,8 +296,8 @@ __device__ __forceinline__ void encrypt_item_g(const DevParams& p, const double*
                                      [&](uint32_t k, u64 a, u64 b) {
                                          const u64x2 u2 = load_pair(c2 + k), w = load_pair(pk2 + k),
                                                      ws = load_pair(pk2s + k);
-                                         store_pair(c2 + k, addmod(a, nt.mul(u2.x, w.x, ws.x), lc.q),
-                                                    addmod(b, nt.mul(u2.y, w.y, ws.y), lc.q));
+                                         store_pair_final(c2 + k, addmod(a, nt.mul(u2.x, w.x, ws.x), lc.q),
+                                                          addmod(b, nt.mul(u2.y, w.y, ws.y), lc.q));
                                      });
         }
     }

@@ -117,8 +117,8 @@ k_encrypt_sp(DevParams p, EncArgs a, long long* ws_all) {
         transform_store<false>(nt, t, in1, [&](int c) { return u64_to_fp(in1(c)); },
                                [&](uint32_t k, u64 x, u64 y) {
                                    const u64x2 u2 = load_pair(c2 + k), w = load_pair(w1 + k), ws = load_pair(w1s + k);
-                                   store_pair(c1 + k, addmod(x, nt.mul(u2.x, w.x, ws.x), lc.q),
-                                              addmod(y, nt.mul(u2.y, w.y, ws.y), lc.q));
+                                   store_pair_final(c1 + k, addmod(x, nt.mul(u2.x, w.x, ws.x), lc.q),
+                                                    addmod(y, nt.mul(u2.y, w.y, ws.y), lc.q));
                                });
         const Packed8<R> e2l = e2.fresh();
         auto in2 = [&](int c) {
@@ -130,8 +130,8 @@ k_encrypt_sp(DevParams p, EncArgs a, long long* ws_all) {
         transform_store<false>(nt, t, in2, [&](int c) { return u64_to_fp(in2(c)); },
                                [&](uint32_t k, u64 x, u64 y) {
                                    const u64x2 u2 = load_pair(c2 + k), w = load_pair(w2 + k), ws = load_pair(w2s + k);
-                                   store_pair(c2 + k, addmod(x, nt.mul(u2.x, w.x, ws.x), lc.q),
-                                              addmod(y, nt.mul(u2.y, w.y, ws.y), lc.q));
+                                   store_pair_final(c2 + k, addmod(x, nt.mul(u2.x, w.x, ws.x), lc.q),
+                                                    addmod(y, nt.mul(u2.y, w.y, ws.y), lc.q));
                                });
     }
 }

@@ -220,6 +220,13 @@ __device__ __forceinline__ void encrypt_item_g(const DevParams& p, const double*
     constexpr int R = G::R, N = G::N;
     const uint32_t L = p.L;
     long long* stash = reinterpret_cast<long long*>(ct + (size_t)(L - 1) * N);
+    // final ciphertext words: non-temporal from the natural-order epilogue,
+    // whose wave writes whole lines; the register epilogue's strided 16-byte
+    // writes measured far slower non-temporal, so they stay ordinary stores
+    auto final_store = [](u64* q, u64 a, u64 b) {
+        if constexpr (REG_EPI) store_pair(q, a, b);
+        else store_pair_final(q, a, b);
+    };
 
     if constexpr (FROM_SLOTS) {
         long long m[R];
@@ -245,7 +252,7 @@ __device__ __forceinline__ void encrypt_item_g(const DevParams& p, const double*
             transform_store<REG_EPI>(nt, t, [&](int c) { return msg.ri(c); }, [&](int c) { return msg.rf(c); },
                                      [&](uint32_t k, u64 a, u64 b) {
                                          const u64x2 z = load_pair(z1 + k);
-                                         store_pair_final(c1 + k, addmod(a, z.x, lc.q), addmod(b, z.y, lc.q));
+                                         final_store(c1 + k, addmod(a, z.x, lc.q), addmod(b, z.y, lc.q));
                                      });
             // c2 = zero2 + NTT(e2')
             const Packed8<R> e2l = e2.fresh();
@@ -255,7 +262,7 @@ __device__ __forceinline__ void encrypt_item_g(const DevParams& p, const double*
                                      [&](int c) { return noise_rf<BGV>(e2l.get(c), p.noise_t, lc); },
                                      [&](uint32_t k, u64 a, u64 b) {
                                          const u64x2 z = load_pair(z2 + k);
-                                         store_pair_final(c2 + k, addmod(a, z.x, lc.q), addmod(b, z.y, lc.q));
+                                         final_store(c2 + k, addmod(a, z.x, lc.q), addmod(b, z.y, lc.q));
                                      });
         }
     } else {
@@ -284,8 +291,8 @@ __device__ __forceinline__ void encrypt_item_g(const DevParams& p, const double*
                                      [&](uint32_t k, u64 a, u64 b) {
                                          const u64x2 u2 = load_pair(c2 + k), w = load_pair(pk1 + k),
                                                      ws = load_pair(pk1s + k);
-                                         store_pair_final(c1 + k, addmod(a, nt.mul(u2.x, w.x, ws.x), lc.q),
-                                                          addmod(b, nt.mul(u2.y, w.y, ws.y), lc.q));
+                                         final_store(c1 + k, addmod(a, nt.mul(u2.x, w.x, ws.x), lc.q),
+                                                     addmod(b, nt.mul(u2.y, w.y, ws.y), lc.q));
                                      });
             // c2 = pk2 u_hat + NTT(e2)
             const Packed8<R> e2l = e2.fresh();
@@ -296,8 +303,8 @@ __device__ __forceinline__ void encrypt_item_g(const DevParams& p, const double*
                                      [&](uint32_t k, u64 a, u64 b) {
                                          const u64x2 u2 = load_pair(c2 + k), w = load_pair(pk2 + k),
                                                      ws = load_pair(pk2s + k);
-                                         store_pair_final(c2 + k, addmod(a, nt.mul(u2.x, w.x, ws.x), lc.q),
-                                                          addmod(b, nt.mul(u2.y, w.y, ws.y), lc.q));
+                                         final_store(c2 + k, addmod(a, nt.mul(u2.x, w.x, ws.x), lc.q),
+                                                     addmod(b, nt.mul(u2.y, w.y, ws.y), lc.q));
                                      });
         }
     }

@@ -251,6 +251,34 @@ def bench_config_table(steps: int, warmup: int, budget_s: float) -> list:
     return rows
 
 
+def bench_encrypt_only(ctx, z, ids, ct, steps: int, warmup: int) -> dict:
+    """Encryption alone from plaintexts encoded beforehand (zinc_encode), the
+    figure reported beside the fused encode + encrypt throughput."""
+    import torch
+
+    b, L, n = ct.shape[0], ct.shape[2], ct.shape[3]
+    pt = torch.empty((b, L, n), dtype=torch.int64, device="cuda")
+    ctx.encode(z, pt)
+    out = {}
+    for name, fn in (("zinc", lambda: ctx.encrypt(pt, ids, ct)), ("vanilla", lambda: ctx.encrypt_vanilla(pt, ids, ct))):
+        settle(fn)
+        for _ in range(max(1, warmup)):
+            fn()
+        torch.cuda.synchronize()
+        a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(steps):
+            fn()
+        e.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(e) / steps
+        out[name] = {"kernel_ms": ms, "enc_per_s": b / (ms / 1e3)}
+        print(f"[bench] encrypt only (pre-encoded) {name}: {out[name]}", file=sys.stderr, flush=True)
+    out["zinc_over_vanilla"] = out["vanilla"]["kernel_ms"] / out["zinc"]["kernel_ms"]
+    del pt
+    return out
+
+
 def bench_elementwise(ctx, ps, batch: int, steps: int, warmup: int) -> dict:
     """The element-wise steps alone (Algorithm 1's additions, Eq. 8's products
     and additions) on `batch` ciphertexts of transform outputs: HBM-bound
@@ -572,6 +600,7 @@ def main():
         # vanilla as a library with a special prime computes it (division by
         # the prime with rounding), the form of the paper's CPU baseline
         line["zinc_over_vanilla_sp"] = res["vanilla_sp"]["ms_per_step"] / res["zinc"]["ms_per_step"]
+    line["encrypt_only"] = bench_encrypt_only(ctx, z, ids, ct, args.steps, args.warmup)
     line["elementwise"] = bench_elementwise(ctx, ps, ws.batch, args.steps, args.warmup)
     if not args.no_mixed:
         del ct, z

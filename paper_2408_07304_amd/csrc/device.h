@@ -19,7 +19,12 @@ typedef uint64_t u64;
 
 // y * w mod q in [0, 2q), for any y < 2^64, w < q, wp = floor(w 2^64 / q).
 __device__ __forceinline__ u64 shoup_lazy(u64 y, u64 w, u64 wp, u64 q) {
-    return y * w - __umul64hi(y, wp) * q;
+    // high word of y wp from 32-bit pieces: each partial sum fits in 64 bits
+    const uint32_t yl = (uint32_t)y, yh = (uint32_t)(y >> 32), pl = (uint32_t)wp, ph = (uint32_t)(wp >> 32);
+    const u64 m1 = (u64)yl * ph + __umulhi(yl, pl);
+    const u64 m2 = (u64)yh * pl + (uint32_t)m1;
+    const u64 hi = (u64)yh * ph + (m1 >> 32) + (m2 >> 32);
+    return y * w - hi * q;
 }
 
 __device__ __forceinline__ u64 csub(u64 x, u64 m) { return x >= m ? x - m : x; }

@@ -294,7 +294,7 @@ __device__ __forceinline__ auto load_tw(const T* p) {
     else return load_pair(p);
 }
 
-// ---- integer path (any modulus below 2^60): Shoup butterflies, [0, 4q) ----
+// ---- integer path (any modulus below 2^60): Shoup butterflies, lazy bounds ----
 
 template <class G, int P>
 __device__ __forceinline__ void fwd_pass(u64 (&v)[G::R], uint32_t t, const u64* __restrict__ tw,

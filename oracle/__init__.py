@@ -11,7 +11,12 @@ Every function cites the passage of the paper it follows:
   * distributions R_q, chi (sigma = 3.2), R_2 (Polynomials and Distributions);
   * the RNS / DFT structure of the Theoretical Analysis section;
   * CKKS encoding, which the paper takes from the CKKS paper (Scheme
-    Flexibility section) -- the canonical-embedding definition is used.
+    Flexibility section) -- the canonical-embedding definition is used;
+  * the BFV (Eq. 12) and BGV (Eq. 13) forms of the same section: BFV's
+    Delta = floor(Q / t) scaling with exact rounding on decryption, BGV's
+    errors scaled by t with the centred CRT value reduced mod t, and the
+    standard batch (slot) encoding mod a prime t = 1 (mod 2N) that both use
+    for vector plaintexts.
 """
 from __future__ import annotations
 

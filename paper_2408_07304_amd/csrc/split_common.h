@@ -210,7 +210,9 @@ __device__ __forceinline__ void encrypt_item_split(const DevParams& p, const dou
         }
     }
 
-    // message transform of limb l into dst (natural order) with epilogue epi(k, value)
+    // message transform of limb l into dst (natural order) with epilogue
+    // epi(k, value_k, value_k+1) on pairs (k even: one 16-byte access; a wave
+    // covers whole lines)
     auto message_ntt = [&](const SplitLimb& sl, const LimbConst& lc, uint32_t l, const Packed8<RS>& elo,
                            const Packed8<RS>& ehi, u64* dst, auto&& epi) {
         const uint32_t tp0 = GS::tpart(0, opaque_tid(t));
@@ -234,14 +236,20 @@ __device__ __forceinline__ void encrypt_item_split(const DevParams& p, const dou
         {
             const uint32_t tt = opaque_tid(t);
 #pragma unroll
-            for (int i = 0; i < RS; ++i) epi(tt + TS * i, sl.canon(tt + TS * i));
+            for (int i = 0; i < RS / 2; ++i) {
+                const uint32_t k = 2 * (tt + TS * i);
+                epi(k, sl.canon(k), sl.canon(k + 1));
+            }
         }
         const uint32_t tp1 = GS::tpart(0, opaque_tid(t));
         sl.run_half(1, [&](int c) { return dst[NH + jp(tp1, c)]; });
         {
             const uint32_t tt = opaque_tid(t);
 #pragma unroll
-            for (int i = 0; i < RS; ++i) epi(NH + tt + TS * i, sl.canon(tt + TS * i));
+            for (int i = 0; i < RS / 2; ++i) {
+                const uint32_t k = 2 * (tt + TS * i);
+                epi(NH + k, sl.canon(k), sl.canon(k + 1));
+            }
         }
     };
     // transform of a small-coefficient polynomial (samples), both halves
@@ -252,7 +260,10 @@ __device__ __forceinline__ void encrypt_item_split(const DevParams& p, const dou
             sl.run_half(h, [&](int c) { return sl.stage0(sl.small(el.lo.get(c)), sl.small(el.hi.get(c)), h); });
             const uint32_t tt = opaque_tid(t);
 #pragma unroll
-            for (int i = 0; i < RS; ++i) epi((uint32_t)h * NH + tt + TS * i, sl.canon(tt + TS * i));
+            for (int i = 0; i < RS / 2; ++i) {
+                const uint32_t k = 2 * (tt + TS * i);
+                epi((uint32_t)h * NH + k, sl.canon(k), sl.canon(k + 1));
+            }
         }
     };
 
@@ -269,8 +280,14 @@ __device__ __forceinline__ void encrypt_item_split(const DevParams& p, const dou
             const u64* z1 = p.zero + (size_t)l * NF;
             const u64* z2 = p.zero + (size_t)(L + l) * NF;
             const Pair8 e1l = e1.fresh();
-            message_ntt(sl, lc, l, e1l.lo, e1l.hi, c1, [&](uint32_t k, u64 v) { c1[k] = addmod(v, z1[k], lc.q); });
-            small_ntt(sl, e2, [&](uint32_t k, u64 v) { c2[k] = addmod(v, z2[k], lc.q); });
+            message_ntt(sl, lc, l, e1l.lo, e1l.hi, c1, [&](uint32_t k, u64 a, u64 b) {
+                const u64x2 z = load_pair(z1 + k);
+                store_pair_final(c1 + k, addmod(a, z.x, lc.q), addmod(b, z.y, lc.q));
+            });
+            small_ntt(sl, e2, [&](uint32_t k, u64 a, u64 b) {
+                const u64x2 z = load_pair(z2 + k);
+                store_pair_final(c2 + k, addmod(a, z.x, lc.q), addmod(b, z.y, lc.q));
+            });
         }
     } else {
         Pair8 u, e1, e2;
@@ -288,11 +305,18 @@ __device__ __forceinline__ void encrypt_item_split(const DevParams& p, const dou
             const u64* pk1s = p.pk_sh + (size_t)l * NF;
             const u64* pk2 = p.pk + (size_t)(M + l) * NF;
             const u64* pk2s = p.pk_sh + (size_t)(M + l) * NF;
-            small_ntt(sl, u, [&](uint32_t k, u64 v) { c2[k] = v; });                       // u_hat
+            small_ntt(sl, u, [&](uint32_t k, u64 a, u64 b) { store_pair(c2 + k, a, b); });   // u_hat
             const Pair8 e1l = e1.fresh();
-            message_ntt(sl, lc, l, e1l.lo, e1l.hi, c1,
-                        [&](uint32_t k, u64 v) { c1[k] = addmod(v, sl.mul(c2[k], pk1[k], pk1s[k]), lc.q); });
-            small_ntt(sl, e2, [&](uint32_t k, u64 v) { c2[k] = addmod(v, sl.mul(c2[k], pk2[k], pk2s[k]), lc.q); });
+            message_ntt(sl, lc, l, e1l.lo, e1l.hi, c1, [&](uint32_t k, u64 a, u64 b) {
+                const u64x2 u2 = load_pair(c2 + k), w = load_pair(pk1 + k), ws = load_pair(pk1s + k);
+                store_pair_final(c1 + k, addmod(a, sl.mul(u2.x, w.x, ws.x), lc.q),
+                                 addmod(b, sl.mul(u2.y, w.y, ws.y), lc.q));
+            });
+            small_ntt(sl, e2, [&](uint32_t k, u64 a, u64 b) {
+                const u64x2 u2 = load_pair(c2 + k), w = load_pair(pk2 + k), ws = load_pair(pk2s + k);
+                store_pair_final(c2 + k, addmod(a, sl.mul(u2.x, w.x, ws.x), lc.q),
+                                 addmod(b, sl.mul(u2.y, w.y, ws.y), lc.q));
+            });
         }
     }
 }

@@ -222,8 +222,8 @@ __device__ __forceinline__ void encrypt_item_split(const DevParams& p, const dou
             const uint32_t k = jp(tp0, c);
             u64 xl, xh;
             if constexpr (FROM_SLOTS) {
-                xl = sl.residue(reduce_signed(stash[k] + elo.get(c), lc));
-                xh = sl.residue(reduce_signed(stash[NH + k] + ehi.get(c), lc));
+                xl = sl.residue(reduce_signed_near(stash[k] + elo.get(c), lc));
+                xh = sl.residue(reduce_signed_near(stash[NH + k] + ehi.get(c), lc));
             } else {
                 const u64* ptl = pt + (size_t)l * NF;
                 xl = sl.residue(csub(ptl[k] + small_mod(elo.get(c), lc.q), lc.q));

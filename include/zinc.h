@@ -226,7 +226,7 @@ zinc_status zinc_bfv_decode(zinc_ctx* ctx, uint64_t t, const uint64_t* d_pt, uin
  * zinc_set_bgv(ctx, t) puts the context in BGV form for the next zinc_keygen
  * and clears its keys and cached Enc(0) (keyed = precomputed = 0); t = 1
  * returns it to the CKKS/BFV form.  t in [2, 2^32) and below every data
- * modulus (ZINC_E_INVAL), N <= 16384 (ZINC_E_PARAM).  A BGV context encrypts
+ * modulus (ZINC_E_INVAL); every ring degree.  A BGV context encrypts
  * residue plaintexts through zinc_encrypt (Zinc, Algorithm 1 with t-scaled
  * errors) and zinc_encrypt_vanilla (Eq. 8 with t-scaled errors) and decrypts
  * through zinc_decrypt; zinc_encrypt_slots, zinc_encrypt_vanilla_sp, the BFV

@@ -442,7 +442,6 @@ zinc_status zinc_set_bgv(zinc_ctx* c, uint64_t t) {
         if (t < 2 || t >= (1ull << 32)) return fail(ZINC_E_INVAL, "zinc_set_bgv: t must be 1 or in [2, 2^32)");
         for (uint32_t l = 0; l < c->L; ++l)
             if (t >= c->q[l]) return fail(ZINC_E_INVAL, "zinc_set_bgv: t must be below every data modulus");
-        if (c->log_n == 15) return fail(ZINC_E_PARAM, "zinc_set_bgv: BGV is built for N <= 16384");
     }
     c->dev.noise_t = t;
     c->keyed = false;

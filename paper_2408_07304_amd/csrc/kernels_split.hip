@@ -13,7 +13,7 @@ namespace zinc {
 
 using namespace split;
 
-template <int SCHEME, bool FROM_SLOTS>
+template <int SCHEME, bool FROM_SLOTS, bool BGV = false>
 __global__ void __launch_bounds__(TS) __attribute__((amdgpu_waves_per_eu(4)))
 k_encrypt_split(DevParams p, EncArgs a) {
     __shared__ u64 lds[LdsWords<NH>::value];
@@ -21,12 +21,13 @@ k_encrypt_split(DevParams p, EncArgs a) {
     const uint32_t t = threadIdx.x, b = blockIdx.x;
     load_cdt(tab, p.cdt, t);
     const uint32_t L = p.L;
-    encrypt_item_split<SCHEME, FROM_SLOTS>(p, a.slots + (size_t)b * a.n_slots, a.n_slots, a.pt + (size_t)b * L * NF,
+    encrypt_item_split<SCHEME, FROM_SLOTS, BGV>(p, a.slots + (size_t)b * a.n_slots, a.n_slots, a.pt + (size_t)b * L * NF,
                                            a.ct_ids[b], a.ct + (size_t)b * 2 * L * NF, lds, tab, t);
 }
 
 // ---------------------------------------------------------------------------
-// key generation, N = 32768 (integer arithmetic), one workgroup per modulus
+// key generation, N = 32768 (integer arithmetic), one workgroup per modulus;
+// under BGV the key error is t e (Eq. 13)
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(TS) k_keygen_split(DevParams p, u64* sk, u64* sk_sh, u64* pk, u64* pk_sh) {
     __shared__ u64 lds[LdsWords<NH>::value];
@@ -37,6 +38,7 @@ __global__ void __launch_bounds__(TS) k_keygen_split(DevParams p, u64* sk, u64* 
     lc.fp = 0;
     const SplitLimb sl(p, lc, l, lds, t);
     const uint32_t M = p.M;
+    const u64 et = p.noise_t > 1 ? p.noise_t : 0;
     Pair8 s, e;
     sample_ternary_split(s, p, ZINC_KEY_ID, TAG_SK, t);
     sample_gauss_split(e, p, tab, ZINC_KEY_ID, TAG_EPK, t);
@@ -53,7 +55,8 @@ __global__ void __launch_bounds__(TS) k_keygen_split(DevParams p, u64* sk, u64* 
             sk_sh[(size_t)l * NF + k] = shoup_companion_dev(v, lc.q);
         }
         const Pair8 eh_ = e.fresh();
-        sl.run_half(h, [&](int c) { return sl.stage0(small_mod(eh_.lo.get(c), lc.q), small_mod(eh_.hi.get(c), lc.q), h); });
+        auto err = [&](int x) { return et ? reduce_signed((long long)x * (long long)et, lc) : small_mod(x, lc.q); };
+        sl.run_half(h, [&](int c) { return sl.stage0(err(eh_.lo.get(c)), err(eh_.hi.get(c)), h); });
         const uint32_t t2 = opaque_tid(t);
 #pragma unroll
         for (int i = 0; i < RS; ++i) {
@@ -250,7 +253,12 @@ hipError_t launch_split_encrypt(const DevParams& p, int scheme, bool from_slots,
                                 uint32_t n_slots, const uint64_t* pt, uint32_t batch, const uint64_t* ct_ids,
                                 uint64_t* ct, hipStream_t s) {
     EncArgs a{slots, n_slots, (const u64*)pt, (const u64*)ct_ids, (u64*)ct};
-    if (scheme == ZINC_SCHEME_ZINC) {
+    if (p.noise_t > 1) {            // BGV: integer plaintexts only
+        if (from_slots) return hipErrorInvalidValue;
+        if (scheme == ZINC_SCHEME_ZINC)
+            hipLaunchKernelGGL((k_encrypt_split<ZINC_SCHEME_ZINC, false, true>), dim3(batch), dim3(TS), 0, s, p, a);
+        else hipLaunchKernelGGL((k_encrypt_split<ZINC_SCHEME_VANILLA, false, true>), dim3(batch), dim3(TS), 0, s, p, a);
+    } else if (scheme == ZINC_SCHEME_ZINC) {
         if (from_slots) hipLaunchKernelGGL((k_encrypt_split<ZINC_SCHEME_ZINC, true>), dim3(batch), dim3(TS), 0, s, p, a);
         else hipLaunchKernelGGL((k_encrypt_split<ZINC_SCHEME_ZINC, false>), dim3(batch), dim3(TS), 0, s, p, a);
     } else {

@@ -2,6 +2,8 @@
 // N = 32768 (split transforms; see kernels_split.hip).
 #pragma once
 
+#include <type_traits>
+
 #include "kernels_common.h"
 
 namespace zinc {
@@ -178,6 +180,12 @@ struct SplitLimb {
     __device__ __forceinline__ u64 residue(u64 r) const {   // canonical or [0, 2q) residue
         return fp() ? (u64)__double_as_longlong(u64_to_fp(r)) : r;
     }
+    // a Gaussian error as the scheme adds it: x, or t x under BGV (Eq. 13)
+    template <bool BGV>
+    __device__ __forceinline__ u64 noise(int x, u64 nt, const LimbConst& lc) const {
+        if constexpr (!BGV) return small(x);
+        else return fp() ? (u64)__double_as_longlong(noise_rf<true>(x, nt, lc)) : noise_ri<true>(x, nt, lc);
+    }
 };
 
 }  // namespace split
@@ -190,12 +198,15 @@ struct SplitLimb {
 // it wrote, before any thread overwrites it.
 // ---------------------------------------------------------------------------
 // Encrypt one ciphertext of ring degree 32768 with all TS threads of the
-// workgroup; lds holds LdsWords<NH> words, tab the chi table.
-template <int SCHEME, bool FROM_SLOTS>
+// workgroup; lds holds LdsWords<NH> words, tab the chi table.  BGV = true
+// (integer plaintexts only): every Gaussian error is scaled by the plaintext
+// modulus p.noise_t (Eq. 13); the ternary u is not.
+template <int SCHEME, bool FROM_SLOTS, bool BGV = false>
 __device__ __forceinline__ void encrypt_item_split(const DevParams& p, const double* slots, uint32_t n_slots,
                                                    const u64* pt, u64 ct_id, u64* ct, u64* lds, const u64* tab,
                                                    uint32_t t) {
     using namespace split;
+    static_assert(!(FROM_SLOTS && BGV), "BGV encrypts integer plaintexts");
     const uint32_t L = p.L;
     long long* stash = reinterpret_cast<long long*>(ct + (size_t)(L - 1) * NF);
 
@@ -226,8 +237,8 @@ __device__ __forceinline__ void encrypt_item_split(const DevParams& p, const dou
                 xh = sl.residue(reduce_signed_near(stash[NH + k] + ehi.get(c), lc));
             } else {
                 const u64* ptl = pt + (size_t)l * NF;
-                xl = sl.residue(csub(ptl[k] + small_mod(elo.get(c), lc.q), lc.q));
-                xh = sl.residue(csub(ptl[NH + k] + small_mod(ehi.get(c), lc.q), lc.q));
+                xl = sl.residue(csub(ptl[k] + noise_ri<BGV>(elo.get(c), p.noise_t, lc), lc.q));
+                xh = sl.residue(csub(ptl[NH + k] + noise_ri<BGV>(ehi.get(c), p.noise_t, lc), lc.q));
             }
             u[c] = sl.stage0(xl, xh, 0);
             dst[NH + k] = sl.stage0(xl, xh, 1);          // half-1 input, read back below
@@ -252,12 +263,16 @@ __device__ __forceinline__ void encrypt_item_split(const DevParams& p, const dou
             }
         }
     };
-    // transform of a small-coefficient polynomial (samples), both halves
-    auto small_ntt = [&](const SplitLimb& sl, const Pair8& e, auto&& epi) {
+    // transform of a small-coefficient polynomial (samples), both halves; an
+    // error polynomial (ERR true) is scaled by t under BGV
+    auto small_ntt = [&](const SplitLimb& sl, const LimbConst& lc, const Pair8& e, auto err, auto&& epi) {
+        constexpr bool S = decltype(err)::value && BGV;
 #pragma unroll 1
         for (int h = 0; h < 2; ++h) {
             const Pair8 el = e.fresh();
-            sl.run_half(h, [&](int c) { return sl.stage0(sl.small(el.lo.get(c)), sl.small(el.hi.get(c)), h); });
+            sl.run_half(h, [&](int c) {
+                return sl.stage0(sl.noise<S>(el.lo.get(c), p.noise_t, lc), sl.noise<S>(el.hi.get(c), p.noise_t, lc), h);
+            });
             const uint32_t tt = opaque_tid(t);
 #pragma unroll
             for (int i = 0; i < RS / 2; ++i) {
@@ -284,7 +299,7 @@ __device__ __forceinline__ void encrypt_item_split(const DevParams& p, const dou
                 const u64x2 z = load_pair(z1 + k);
                 store_pair_final(c1 + k, addmod(a, z.x, lc.q), addmod(b, z.y, lc.q));
             });
-            small_ntt(sl, e2, [&](uint32_t k, u64 a, u64 b) {
+            small_ntt(sl, lc, e2, std::true_type{}, [&](uint32_t k, u64 a, u64 b) {
                 const u64x2 z = load_pair(z2 + k);
                 store_pair_final(c2 + k, addmod(a, z.x, lc.q), addmod(b, z.y, lc.q));
             });
@@ -305,14 +320,14 @@ __device__ __forceinline__ void encrypt_item_split(const DevParams& p, const dou
             const u64* pk1s = p.pk_sh + (size_t)l * NF;
             const u64* pk2 = p.pk + (size_t)(M + l) * NF;
             const u64* pk2s = p.pk_sh + (size_t)(M + l) * NF;
-            small_ntt(sl, u, [&](uint32_t k, u64 a, u64 b) { store_pair(c2 + k, a, b); });   // u_hat
+            small_ntt(sl, lc, u, std::false_type{}, [&](uint32_t k, u64 a, u64 b) { store_pair(c2 + k, a, b); });   // u_hat
             const Pair8 e1l = e1.fresh();
             message_ntt(sl, lc, l, e1l.lo, e1l.hi, c1, [&](uint32_t k, u64 a, u64 b) {
                 const u64x2 u2 = load_pair(c2 + k), w = load_pair(pk1 + k), ws = load_pair(pk1s + k);
                 store_pair_final(c1 + k, addmod(a, sl.mul(u2.x, w.x, ws.x), lc.q),
                                  addmod(b, sl.mul(u2.y, w.y, ws.y), lc.q));
             });
-            small_ntt(sl, e2, [&](uint32_t k, u64 a, u64 b) {
+            small_ntt(sl, lc, e2, std::true_type{}, [&](uint32_t k, u64 a, u64 b) {
                 const u64x2 u2 = load_pair(c2 + k), w = load_pair(pk2 + k), ws = load_pair(pk2s + k);
                 store_pair_final(c2 + k, addmod(a, sl.mul(u2.x, w.x, ws.x), lc.q),
                                  addmod(b, sl.mul(u2.y, w.y, ws.y), lc.q));

@@ -315,7 +315,6 @@ static zinc_status check_batch(const char* fn, uint32_t batch, std::initializer_
 // rounding offsets), allocated and freed in stream order around the launch.
 static zinc_status encrypt_sp(zinc_ctx* c, bool from_slots, const double* slots, uint32_t n_slots,
                               const uint64_t* pt, uint32_t batch, const uint64_t* ids, uint64_t* ct, void* stream) {
-    if (c->log_n == 15) return fail(ZINC_E_PARAM, "special-prime vanilla is built for N <= 16384");
     hipStream_t s = (hipStream_t)stream;
     int64_t* ws = nullptr;
     hipError_t e = hipMallocAsync((void**)&ws, (size_t)batch * 3 * c->n * sizeof(int64_t), s);

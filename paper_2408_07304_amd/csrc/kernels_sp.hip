@@ -171,6 +171,7 @@ hipError_t launch_encrypt_sp(const DevParams& p, bool from_slots, const double* 
             hipLaunchKernelGGL((k_encrypt_sp<LN, false>), dim3(batch), dim3(Cfg<LN>::G::T), 0, s, p, a, w); \
         break;
     switch (p.log_n) {
+        case 15: return launch_split_encrypt_sp(p, from_slots, slots, n_slots, pt, batch, ct_ids, ct, ws, s);
         F(12)
         F(13)
         F(14)

@@ -76,47 +76,6 @@ __global__ void __launch_bounds__(TS) k_keygen_split(DevParams p, u64* sk, u64* 
     }
 }
 
-// ---------------------------------------------------------------------------
-// inverse transform, N = 32768: both half inverses, then the pairing stage
-// (Gentleman-Sande with psi^-brv(1)) and N^-1.  xin(k) gives input k in
-// [0, 2q); out(k, v) receives canonical outputs.
-// ---------------------------------------------------------------------------
-template <class In, class Out>
-__device__ __forceinline__ void intt_split(const DevParams& p, const LimbConst& lc, uint32_t l, u64* lds,
-                                           uint32_t t, In xin, Out out) {
-    constexpr int PL = GS::NPASS - 1;
-    const u64 q = lc.q, q2 = lc.q2;
-    u64 lo[RS];
-#pragma unroll 1
-    for (int h = 0; h < 2; ++h) {
-        __syncthreads();
-        {
-            const uint32_t tt = opaque_tid(t);
-#pragma unroll
-            for (int i = 0; i < RS; ++i) lds[pad(tt + TS * i)] = xin((uint32_t)h * NH + tt + TS * i);
-        }
-        __syncthreads();
-        u64 v[RS];
-        lds_get<GS, PL>(lds, v, t);
-        ntt_inv<GS>(v, lds, p.itw, l, q, q2, t, 2u + (uint32_t)h, NF);
-        if (h == 0) {
-#pragma unroll
-            for (int c = 0; c < RS; ++c) lo[c] = v[c];
-        } else {
-            const size_t o = ((size_t)l * NF + 1) * 2;
-            const u64 iw = p.itw[o], iws = p.itw[o + 1];
-            const uint32_t tp0 = GS::tpart(0, t);
-#pragma unroll
-            for (int c = 0; c < RS; ++c) {
-                u64 x = lo[c], y = v[c];
-                gs_bfly(x, y, iw, iws, q, q2);
-                out(jp(tp0, c), csub(shoup_lazy(x, lc.ninv, lc.ninv_sh, q), q));
-                out(NH + jp(tp0, c), csub(shoup_lazy(y, lc.ninv, lc.ninv_sh, q), q));
-            }
-        }
-    }
-}
-
 __global__ void __launch_bounds__(TS) k_decrypt_split(DevParams p, const u64* ct, u64* pt) {
     __shared__ u64 lds[LdsWords<NH>::value];
     const uint32_t t = threadIdx.x, l = blockIdx.x, b = blockIdx.y, L = p.L;

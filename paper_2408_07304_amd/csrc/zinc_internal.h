@@ -243,5 +243,8 @@ hipError_t launch_split_decode(const DevParams& p, const uint64_t* pt, uint32_t 
                                double* slots, hipStream_t s);
 hipError_t launch_split_ntt(const DevParams& p, bool inverse, uint32_t limb, uint64_t* poly,
                             uint32_t n_polys, hipStream_t s);
+hipError_t launch_split_encrypt_sp(const DevParams& p, bool from_slots, const double* slots, uint32_t n_slots,
+                                   const uint64_t* pt, uint32_t batch, const uint64_t* ct_ids, uint64_t* ct,
+                                   int64_t* ws, hipStream_t s);
 
 }  // namespace zinc

@@ -196,8 +196,8 @@ zinc_status zinc_decode(zinc_ctx* ctx, const uint64_t* d_pt, uint32_t batch, dou
  * a_j = pk_j u + e_j, divided by p with rounding (coefficient-wise
  * round(a_j / p), which leaves the L data limbs), then the message added to
  * c1.  Same layouts as zinc_encrypt_vanilla; costlier (the special limb's
- * transforms and two inverse transforms); N <= 16384 (ZINC_E_PARAM for
- * 32768).  zinc_encrypt_slots with ZINC_SCHEME_VANILLA_SP is the fused form.
+ * transforms and two inverse transforms); every ring degree.
+ * zinc_encrypt_slots with ZINC_SCHEME_VANILLA_SP is the fused form.
  * Scratch of batch * 3 * N * 8 bytes is allocated and freed in `stream`'s
  * order (hipMallocAsync). */
 zinc_status zinc_encrypt_vanilla_sp(zinc_ctx* ctx, const uint64_t* d_pt, uint32_t batch,

@@ -82,10 +82,10 @@ def test_bfv_slots_through_encryption(name):
         assert np.array_equal(from_dev(mm, np.int64), v), scheme
 
 
-def test_bgv_slots_through_encryption():
+@pytest.mark.parametrize("name,t", [("n8192", 65537), ("n32768", 786433)])
+def test_bgv_slots_through_encryption(name, t):
     torch = torch_cuda()
-    t = 65537
-    c = zinc.context_for(PARAM_SETS["n8192"])
+    c = zinc.context_for(PARAM_SETS[name])
     c.set_bgv(t)
     c.keygen()
     c.precompute()
@@ -96,7 +96,7 @@ def test_bgv_slots_through_encryption():
     pt = empty_u64(B, L, n)
     c.bgv_encode(m, pt)
     for scheme in (zinc.ZINC_SCHEME_ZINC, zinc.ZINC_SCHEME_VANILLA):
-        say(f"n8192 BGV slots scheme={scheme}")
+        say(f"{name} BGV slots scheme={scheme}")
         ct = empty_u64(B, 2, L, n)
         (c.encrypt if scheme == zinc.ZINC_SCHEME_ZINC else c.encrypt_vanilla)(pt, ids([4, 8]), ct)
         dec = empty_u64(B, L, n)

@@ -16,9 +16,10 @@
 // each inverse transform then writes D_j over a_j in place (it reads all of
 // its input before any thread writes output, and parks its half-0 result in
 // the first half of the same row).  D_j and the message are read
-// back on the data limbs by the thread that wrote them.  The inputs
-// (e_j + D_j) p^-1 (+ m) are recomputed for the second half of each transform
-// rather than stashed: c2 already holds NTT(u).  Every transform takes the
+// back on the data limbs by the thread that wrote them.  The second half's
+// input of the c1 transform waits in the upper half of c1, as in the CKKS
+// kernels; that of the c2 transform, (e_2 + D_2) p^-1, is recomputed, since
+// c2 already holds NTT(u).  Every transform takes the
 // integer (Shoup) path, exact for any modulus, as key generation does.
 #include "split_common.h"
 
@@ -127,16 +128,26 @@ k_encrypt_sp_split(DevParams p, EncArgs a, long long* ws_all) {
         auto in2 = [&](uint32_t k, int e) {
             return csub(shoup_lazy(reduce_signed(e + wd2[k], lc), lc.pinv, lc.pinv_sh, lc.q), lc.q);
         };
-        // dst = NTT(input) + pkp * NTT(u), both halves
-        auto enc_ntt = [&](const Pair8& e, auto&& in, const u64* w, const u64* ws, u64* dst) {
+        // dst = NTT(input) + pkp * NTT(u), both halves.  STASH: the second
+        // half's stage-0 output waits in the upper half of dst (read back by the
+        // thread that wrote it before any thread stores there); otherwise the
+        // input is recomputed for the second half.
+        auto enc_ntt = [&](const Pair8& e, auto&& in, const u64* w, const u64* ws, u64* dst, auto stash) {
+            constexpr bool STASH = decltype(stash)::value;
 #pragma unroll 1
             for (int h = 0; h < 2; ++h) {
                 const Pair8 el = e.fresh();
                 const uint32_t tp0 = GS::tpart(0, opaque_tid(t));
-                sl.run_half(h, [&](int c) {
-                    const uint32_t k = jp(tp0, c);
-                    return sl.stage0(sl.residue(in(k, el.lo.get(c))), sl.residue(in(NH + k, el.hi.get(c))), h);
-                });
+                if (STASH && h == 1) {
+                    sl.run_half(1, [&](int c) { return dst[NH + jp(tp0, c)]; });
+                } else {
+                    sl.run_half(h, [&](int c) {
+                        const uint32_t k = jp(tp0, c);
+                        const u64 xl = sl.residue(in(k, el.lo.get(c))), xh = sl.residue(in(NH + k, el.hi.get(c)));
+                        if constexpr (STASH) dst[NH + k] = sl.stage0(xl, xh, 1);
+                        return sl.stage0(xl, xh, h);
+                    });
+                }
                 const uint32_t tt = opaque_tid(t);
 #pragma unroll
                 for (int i = 0; i < RS / 2; ++i) {
@@ -147,8 +158,8 @@ k_encrypt_sp_split(DevParams p, EncArgs a, long long* ws_all) {
                 }
             }
         };
-        enc_ntt(e1, in1, p.pkp + (size_t)l * NF, p.pkp_sh + (size_t)l * NF, c1);
-        enc_ntt(e2, in2, p.pkp + (size_t)(L + l) * NF, p.pkp_sh + (size_t)(L + l) * NF, c2);
+        enc_ntt(e1, in1, p.pkp + (size_t)l * NF, p.pkp_sh + (size_t)l * NF, c1, std::true_type{});
+        enc_ntt(e2, in2, p.pkp + (size_t)(L + l) * NF, p.pkp_sh + (size_t)(L + l) * NF, c2, std::false_type{});
     }
 }
 

@@ -322,6 +322,25 @@ def test_state_and_range_errors():
     c.close()
 
 
+def _check_one(c, P, scheme, key, z, cid, got, where):
+    """One fused ciphertext `got` of slot vector z against the oracle: c2
+    bit-exact, c1 equal up to NTT(delta) with delta in {-1, 0, 1} on the
+    oracle's rounding-tie set (the difference's inverse NTT taken by the
+    library's own INTT, which is checked bit-exact above)."""
+    want = oracle.encrypt_slots(P, scheme, key, z, cid)
+    assert np.array_equal(got[1], want[1]), where
+    if np.array_equal(got[0], want[0]):
+        return
+    m, fr = oracle.encode(P, z)
+    tie = np.abs(np.abs(fr) - 0.5) <= tie_tau(P.n, np.abs(m).max())
+    for l, q in enumerate(P.data_moduli):
+        diff = ((got[0, l].astype(object) - want[0, l].astype(object)) % q).astype(np.uint64)
+        d = to_dev(diff[None, :])
+        c.ntt_inverse(l, d)
+        delta = centred(from_dev(d)[0], q)
+        assert np.abs(delta).max() <= 1 and np.all(tie[delta != 0]), (where, l)
+
+
 def _check_fused_against_oracle(name, w, picks, scheme):
     """Full-size batch in the launch configuration the benchmark times; sampled
     ciphertexts checked one by one against the oracle: c2 bit-exact, c1 equal
@@ -346,18 +365,7 @@ def _check_fused_against_oracle(name, w, picks, scheme):
     got = {i: sel[k] for k, i in enumerate(picks)}
     key = zero if scheme == zinc.ZINC_SCHEME_ZINC else pk
     for i in picks:
-        want = oracle.encrypt_slots(P, scheme, key, z[i], i)
-        assert np.array_equal(got[i][1], want[1]), i
-        if np.array_equal(got[i][0], want[0]):
-            continue
-        m, fr = oracle.encode(P, z[i])
-        tie = np.abs(np.abs(fr) - 0.5) <= tie_tau(P.n, np.abs(m).max())
-        for l, q in enumerate(P.data_moduli):
-            diff = ((got[i][0, l].astype(object) - want[0, l].astype(object)) % q).astype(np.uint64)
-            d = to_dev(diff[None, :])
-            c.ntt_inverse(l, d)
-            delta = centred(from_dev(d)[0], q)
-            assert np.abs(delta).max() <= 1 and np.all(tie[delta != 0]), (i, l)
+        _check_one(c, P, scheme, key, z[i], i, got[i], i)
     return got
 
 
@@ -393,15 +401,31 @@ def test_table2_shapes_at_paper_parameters(scheme):
         c.encrypt_slots(scheme, to_dev(z), ids(range(first, first + 3)), ct)
         got = from_dev(ct)
         for i in range(3):
-            want = oracle.encrypt_slots(P, scheme, key, z[i], first + i)
-            assert np.array_equal(got[i][1], want[1]), (d.name, i)
-            if np.array_equal(got[i][0], want[0]):
-                continue
-            m, fr = oracle.encode(P, z[i])
-            tie = np.abs(np.abs(fr) - 0.5) <= tie_tau(P.n, np.abs(m).max())
-            for l, q in enumerate(P.data_moduli):
-                diff = ((got[i][0, l].astype(object) - want[0, l].astype(object)) % q).astype(np.uint64)
-                dd = to_dev(diff[None, :])
-                c.ntt_inverse(l, dd)
-                delta = centred(from_dev(dd)[0], q)
-                assert np.abs(delta).max() <= 1 and np.all(tie[delta != 0]), (d.name, i, l)
+            _check_one(c, P, scheme, key, z[i], first + i, got[i], (d.name, i))
+
+
+@pytest.mark.parametrize("scheme", SCHEMES + [zinc.ZINC_SCHEME_VANILLA_SP])
+def test_table2_hg38_launch_configuration(scheme):
+    """hg38's shape at the paper's parameters in the launch configuration the
+    benchmark times (the whole dataset's rows, launches of 1,024 rows into one
+    reused buffer): the first full launch and the ragged last one (632 rows,
+    identifiers up to 34,423), sampled rows against the oracle."""
+    torch = torch_cuda()
+    c = gpu_ctx("n32768_q16")
+    P, sh, pk, zero = oracle_keys("n32768_q16")
+    key = zero if scheme == zinc.ZINC_SCHEME_ZINC else pk
+    d = next(x for x in TABLE2 if x.name == "hg38")
+    chunk = 1024
+    rows = dataset_rows(d, 0, d.rows)
+    ids_all = ids(range(d.rows))
+    z_all = to_dev(rows)
+    ct = empty_u64(chunk, 2, P.L, P.n)
+    last = (d.rows - 1) // chunk * chunk
+    for s0, picks in ((0, [0, 511, 1023]), (last, [0, d.rows - 1 - last])):
+        n = min(chunk, d.rows - s0)
+        say(f"hg38 rows {s0}..{s0 + n - 1} scheme={scheme}")
+        c.encrypt_slots(scheme, z_all[s0:s0 + n], ids_all[s0:s0 + n], ct[:n])
+        sel = from_dev(ct[torch.tensor(picks, device="cuda")].contiguous())
+        for k, i in enumerate(picks):
+            _check_one(c, P, scheme, key, rows[s0 + i], s0 + i, sel[k], s0 + i)
+    del ct

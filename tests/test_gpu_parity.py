@@ -369,7 +369,8 @@ def _check_fused_against_oracle(name, w, picks, scheme):
     return got
 
 
-@pytest.mark.parametrize("scheme", SCHEMES)
+# the special-prime form too: the benchmark times it on this batch
+@pytest.mark.parametrize("scheme", SCHEMES + [zinc.ZINC_SCHEME_VANILLA_SP])
 def test_full_batch_n8192_sampled(scheme):
     _check_fused_against_oracle("n8192", W_MAIN, [0, 1, 511, 1023], scheme)
 

@@ -39,7 +39,8 @@
  * device fault surfaces at the caller's next synchronisation.  Range
  * violations found on the device (a slot value whose scaled magnitude reaches
  * 2^62, a decoded coefficient outside the limb-0 lift range) set a sticky flag
- * read by zinc_device_errors.
+ * read by zinc_device_errors.  So does a direct encryption call given a
+ * reserved identifier (>= 2^63): that ciphertext is not written.
  *
  * Threads: a context is read-only after zinc_precompute; encryption calls on
  * one context may run concurrently on different streams (the batch codec's
@@ -286,7 +287,11 @@ zinc_status zinc_add(zinc_ctx* ctx, const uint64_t* d_a, const uint64_t* d_b, ui
 
 /* Read and clear the context's sticky device error flags (synchronises the
  * device): bit 0 = slot magnitude out of range in encode, bit 1 = coefficient
- * outside the limb-0 lift range in decode. */
+ * outside the limb-0 lift range in decode, bit 2 = an encryption call
+ * (zinc_encrypt, zinc_encrypt_vanilla, zinc_encrypt_vanilla_sp,
+ * zinc_encrypt_slots) was given an identifier >= 2^63; the ciphertexts with
+ * such identifiers were left unwritten, since the reserved ones select the
+ * randomness of the keys and of the cached Enc(0). */
 zinc_status zinc_device_errors(zinc_ctx* ctx, uint32_t* flags);
 
 /* ---- mixed-shape batches (one persistent launch over several contexts) ----
@@ -295,7 +300,10 @@ zinc_status zinc_device_errors(zinc_ctx* ctx, uint32_t* flags);
  * of its ciphertext ([2][L][N] of its context) in the ciphertext buffer, and its
  * ct_id.  zinc_plan_create copies the items to the device and sorts them by
  * cost; the plan keeps pointers to the contexts, which must outlive it.
- * zinc_plan_launch encrypts every item in one persistent launch on `stream`:
+ * zinc_plan_launch encrypts every item in one persistent launch on `stream`;
+ * n_slot_words and n_ct_words are the lengths of d_slots (float64 words) and
+ * d_ct (uint64 words), and a buffer that ends before some item's slots or
+ * ciphertext is rejected (ZINC_E_INVAL) before anything is launched.  Launch:
  * the first call records the launch sequence as a HIP graph (on a private
  * stream, so any caller stream works, the null stream included), later calls
  * with the same buffers replay it, and new buffers are recorded again.  The
@@ -311,7 +319,8 @@ typedef struct zinc_item {
 
 zinc_status zinc_plan_create(zinc_ctx* const* ctxs, uint32_t n_ctx, const zinc_item* items,
                              uint32_t n_items, int scheme, zinc_plan** out);
-zinc_status zinc_plan_launch(zinc_plan* plan, const double* d_slots, uint64_t* d_ct, void* stream);
+zinc_status zinc_plan_launch(zinc_plan* plan, const double* d_slots, uint64_t n_slot_words, uint64_t* d_ct,
+                             uint64_t n_ct_words, void* stream);
 zinc_status zinc_plan_destroy(zinc_plan* plan);
 
 /* ---- serving: admission, continuous batching, latency ---------------------
@@ -332,8 +341,13 @@ zinc_status zinc_plan_destroy(zinc_plan* plan);
  * Plaintext k of a request reads the N/2 slots at d_slots + slot_off + k*N/2,
  * gets ct_id + k, and writes its ciphertext at ct_off + k*2*L*N of the output
  * base: d_ct if the configuration gives one, otherwise the server's own arena
- * (hbm_budget bytes allocated at creation; the request's ciphertexts are
- * discarded when it completes, which suits load generation).  Outputs are
+ * (hbm_budget bytes allocated at creation).  In the arena, a completed
+ * request's ciphertexts are either discarded at once (retain_outputs = 0,
+ * which suits load generation) or kept (retain_outputs = 1) until the caller,
+ * having read them through zinc_server_output, calls zinc_server_release;
+ * kept outputs hold their share of the budget, so admission waits for
+ * releases.  A request whose slots (or, with d_ct, ciphertexts) would reach
+ * beyond slots_len (ct_len) is refused at submission.  Outputs are
  * bit-identical to separate launches with the same ct_ids.
  * The server's streams are its own (non-blocking, default priority): inputs
  * must be complete on the device before their requests are submitted.  Times
@@ -344,11 +358,14 @@ typedef struct zinc_server_config {
     int scheme;               /* ZINC_SCHEME_VANILLA or ZINC_SCHEME_ZINC              */
     uint32_t n_streams;       /* concurrent batches, 1..16                            */
     uint32_t max_batch;       /* plaintexts per launch, 1..65536                      */
-    uint32_t reserved;
+    uint32_t retain_outputs;  /* 1: arena outputs kept until zinc_server_release
+                                 (needs d_ct NULL); 0: discarded on completion        */
     uint64_t hbm_budget;      /* bytes of ciphertext admitted at once; 0: half of the
                                  device's free memory at creation                     */
     const double* d_slots;    /* base of every request's slots                        */
     uint64_t* d_ct;           /* base of every request's output, or NULL (arena)      */
+    uint64_t slots_len;       /* float64 words of d_slots (> 0)                       */
+    uint64_t ct_len;          /* uint64 words of d_ct (> 0 when d_ct is given)        */
 } zinc_server_config;
 
 typedef struct zinc_request {
@@ -367,6 +384,9 @@ typedef struct zinc_request_times {
     uint64_t done_ns;         /* its batch's completion was observed                  */
     uint32_t batch;           /* sequence number of its batch                         */
     uint32_t stream;          /* stream index that ran the batch                      */
+    uint64_t dev_start_ns;    /* device interval of its batch: HIP timing events      */
+    uint64_t dev_end_ns;      /* before and after the launch, in nanoseconds since a
+                                 reference event recorded at zinc_server_create      */
 } zinc_request_times;
 
 /* The server keeps pointers to the contexts, which must outlive it; every
@@ -382,7 +402,20 @@ zinc_status zinc_server_submit(zinc_server* srv, const zinc_request* req, uint64
 zinc_status zinc_server_progress(zinc_server* srv, uint32_t* n_done);
 /* *done = 1 and *times filled once the request has completed, else *done = 0. */
 zinc_status zinc_server_query(zinc_server* srv, uint64_t ticket, int* done, zinc_request_times* times);
-/* Progress until every submitted request has completed. */
+/* Retained outputs (retain_outputs = 1): *d_out = the device address of a
+ * completed request's ciphertexts, n_pt * 2 * L * N uint64 words in the
+ * server's arena, valid until zinc_server_release(srv, ticket).  ZINC_E_STATE
+ * if the server does not retain outputs, or the request has not completed or
+ * was already released. */
+zinc_status zinc_server_output(zinc_server* srv, uint64_t ticket, uint64_t** d_out);
+/* The same output copied (device to device, asynchronously on `stream`) into
+ * caller memory d_dst of dst_words uint64 words (ZINC_E_INVAL if shorter). */
+zinc_status zinc_server_read_output(zinc_server* srv, uint64_t ticket, uint64_t* d_dst, uint64_t dst_words,
+                                    void* stream);
+zinc_status zinc_server_release(zinc_server* srv, uint64_t ticket);
+/* Progress until every submitted request has completed.  With retained
+ * outputs, ZINC_E_STATE if waiting requests can only be admitted after some
+ * outputs are released. */
 zinc_status zinc_server_drain(zinc_server* srv);
 /* Waits for the server's streams, then frees its resources. */
 zinc_status zinc_server_destroy(zinc_server* srv);
@@ -391,7 +424,7 @@ zinc_status zinc_server_destroy(zinc_server* srv);
  * when the clock reaches arrival_ns[r] (nanoseconds after the replay starts,
  * non-decreasing), runs zinc_server_progress in between, drains, and writes
  * per-request times (relative to the replay start, submit_ns = the scheduled
- * arrival) to times[n_req]. */
+ * arrival) to times[n_req].  retain_outputs must be 0. */
 zinc_status zinc_serve_trace(zinc_ctx* const* ctxs, uint32_t n_ctx, const zinc_server_config* cfg,
                              const zinc_request* reqs, const uint64_t* arrival_ns, uint32_t n_req,
                              zinc_request_times* times);

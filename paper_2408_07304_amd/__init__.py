@@ -64,8 +64,8 @@ class zinc_item(ctypes.Structure):
 
 class zinc_server_config(ctypes.Structure):
     _fields_ = [("scheme", ctypes.c_int), ("n_streams", ctypes.c_uint32), ("max_batch", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32), ("hbm_budget", ctypes.c_uint64), ("d_slots", ctypes.c_void_p),
-                ("d_ct", ctypes.c_void_p)]
+                ("retain_outputs", ctypes.c_uint32), ("hbm_budget", ctypes.c_uint64), ("d_slots", ctypes.c_void_p),
+                ("d_ct", ctypes.c_void_p), ("slots_len", ctypes.c_uint64), ("ct_len", ctypes.c_uint64)]
 
 
 class zinc_request(ctypes.Structure):
@@ -75,13 +75,14 @@ class zinc_request(ctypes.Structure):
 
 class zinc_request_times(ctypes.Structure):
     _fields_ = [("submit_ns", ctypes.c_uint64), ("admit_ns", ctypes.c_uint64), ("launch_ns", ctypes.c_uint64),
-                ("done_ns", ctypes.c_uint64), ("batch", ctypes.c_uint32), ("stream", ctypes.c_uint32)]
+                ("done_ns", ctypes.c_uint64), ("batch", ctypes.c_uint32), ("stream", ctypes.c_uint32),
+                ("dev_start_ns", ctypes.c_uint64), ("dev_end_ns", ctypes.c_uint64)]
 
 
 # numpy layouts of zinc_request and zinc_request_times (arrays of requests)
 REQUEST_FIELDS = [("ctx_idx", "<u4"), ("n_pt", "<u4"), ("slot_off", "<u8"), ("ct_off", "<u8"), ("ct_id", "<u8")]
 TIMES_FIELDS = [("submit_ns", "<u8"), ("admit_ns", "<u8"), ("launch_ns", "<u8"), ("done_ns", "<u8"),
-                ("batch", "<u4"), ("stream", "<u4")]
+                ("batch", "<u4"), ("stream", "<u4"), ("dev_start_ns", "<u8"), ("dev_end_ns", "<u8")]
 
 _lib = None
 _vp = ctypes.c_void_p
@@ -113,7 +114,7 @@ _SIGS = {
     "zinc_device_errors": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_uint32)]),
     "zinc_plan_create": (ctypes.c_int, [ctypes.POINTER(_vp), _u32, ctypes.POINTER(zinc_item), _u32,
                                         ctypes.c_int, ctypes.POINTER(_vp)]),
-    "zinc_plan_launch": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "zinc_plan_launch": (ctypes.c_int, [_vp, _vp, ctypes.c_uint64, _vp, ctypes.c_uint64, _vp]),
     "zinc_plan_destroy": (ctypes.c_int, [_vp]),
     "zinc_server_create": (ctypes.c_int, [ctypes.POINTER(_vp), _u32, ctypes.POINTER(zinc_server_config),
                                           ctypes.POINTER(_vp)]),
@@ -121,6 +122,9 @@ _SIGS = {
     "zinc_server_progress": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_uint32)]),
     "zinc_server_query": (ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int),
                                          ctypes.POINTER(zinc_request_times)]),
+    "zinc_server_output": (ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.POINTER(_vp)]),
+    "zinc_server_read_output": (ctypes.c_int, [_vp, ctypes.c_uint64, _vp, ctypes.c_uint64, _vp]),
+    "zinc_server_release": (ctypes.c_int, [_vp, ctypes.c_uint64]),
     "zinc_server_drain": (ctypes.c_int, [_vp]),
     "zinc_server_destroy": (ctypes.c_int, [_vp]),
     "zinc_serve_trace": (ctypes.c_int, [ctypes.POINTER(_vp), _u32, ctypes.POINTER(zinc_server_config), _vp, _vp,
@@ -166,15 +170,35 @@ def _check(status: int):
         raise ZincError(status, last_error())
 
 
-def _ptr(t):
-    """Device pointer of a tensor (or None)."""
-    if t is None:
-        return None
-    if isinstance(t, int):
-        return t
+def _buf(t, name: str, dtype: str, numel: int):
+    """Device pointer of `t` after checking that it is a contiguous torch
+    tensor in GPU memory of dtype `dtype` ("int64" carries uint64 data,
+    "float64") holding at least `numel` elements.  A host tensor, a wrong dtype
+    or a short buffer would let the kernels read or write outside it, so each
+    raises here, before anything reaches the library."""
+    import torch
+    if not all(hasattr(t, a) for a in ("data_ptr", "device", "dtype", "numel", "is_contiguous")):
+        raise TypeError(f"{name} must be a torch tensor in GPU memory, not {type(t).__name__}")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be in GPU memory (it is on {t.device})")
+    if t.dtype != getattr(torch, dtype):
+        raise TypeError(f"{name} must be torch.{dtype} (it is {t.dtype})")
     if not t.is_contiguous():
-        raise ValueError("device buffers must be contiguous")
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() < numel:
+        raise ValueError(f"{name} holds {t.numel()} elements; the call needs {numel}")
     return t.data_ptr()
+
+
+def _opt_buf(t, name: str, dtype: str, numel: int):
+    return None if t is None else _buf(t, name, dtype, numel)
+
+
+def _batch(t, name: str) -> int:
+    """Leading dimension of a batched buffer (the batch size the call takes)."""
+    if getattr(t, "ndim", 0) < 1:
+        raise ValueError(f"{name} must have a leading batch dimension")
+    return int(t.shape[0])
 
 
 def _stream(stream):
@@ -195,7 +219,9 @@ def _u64_tensor(values, device):
 
 class Context:
     """One parameter set (ring degree, moduli chain, scale, seed) with its
-    device-resident tables, keys and Zinc cache."""
+    device-resident tables, keys and Zinc cache.  Every method checks its
+    buffers (GPU memory, dtype, contiguity, length) against the sizes the
+    call implies; uint64 data travels in int64 tensors."""
 
     def __init__(self, log_n: int, bits=None, scale: float = 2.0 ** 40, seed: int = 0, moduli=None,
                  sigma: float = 3.2):
@@ -228,6 +254,15 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    # element counts per batch entry
+    @property
+    def pt_words(self) -> int:
+        return self.L * self.n
+
+    @property
+    def ct_words(self) -> int:
+        return 2 * self.L * self.n
 
     def info(self) -> dict:
         i = zinc_info()
@@ -271,30 +306,53 @@ class Context:
     def precompute(self, stream=None):
         _check(load_library().zinc_precompute(self.handle, _stream(stream)))
 
+    def _slots(self, slots):
+        """(pointer, n_slots, batch) of a [batch][n_slots] float64 slot buffer."""
+        if getattr(slots, "ndim", 0) != 2:
+            raise ValueError("slots must be a [batch][n_slots] tensor")
+        b, ns = int(slots.shape[0]), int(slots.shape[1])
+        return _buf(slots, "slots", "float64", b * ns), ns, b
+
     def encode(self, slots, out, stream=None):
-        b = slots.shape[0]
-        _check(load_library().zinc_encode(self.handle, _ptr(slots), slots.shape[1], b, _ptr(out), _stream(stream)))
+        ps, ns, b = self._slots(slots)
+        _check(load_library().zinc_encode(self.handle, ps, ns, b, _buf(out, "out", "int64", b * self.pt_words),
+                                          _stream(stream)))
+        return out
+
+    def _encrypt_pt(self, fn, pt, ct_ids, out, stream):
+        b = _batch(pt, "pt")
+        _check(fn(self.handle, _buf(pt, "pt", "int64", b * self.pt_words), b, _buf(ct_ids, "ct_ids", "int64", b),
+                  _buf(out, "out", "int64", b * self.ct_words), _stream(stream)))
         return out
 
     def encrypt_vanilla(self, pt, ct_ids, out, stream=None):
-        _check(load_library().zinc_encrypt_vanilla(self.handle, _ptr(pt), pt.shape[0], _ptr(ct_ids), _ptr(out),
-                                                   _stream(stream)))
-        return out
+        return self._encrypt_pt(load_library().zinc_encrypt_vanilla, pt, ct_ids, out, stream)
 
     def encrypt_vanilla_sp(self, pt, ct_ids, out, stream=None):
         """Vanilla with division by the special prime (a SEAL-style baseline)."""
-        _check(load_library().zinc_encrypt_vanilla_sp(self.handle, _ptr(pt), pt.shape[0], _ptr(ct_ids), _ptr(out),
-                                                      _stream(stream)))
+        return self._encrypt_pt(load_library().zinc_encrypt_vanilla_sp, pt, ct_ids, out, stream)
+
+    def encrypt(self, pt, ct_ids, out, stream=None):
+        return self._encrypt_pt(load_library().zinc_encrypt, pt, ct_ids, out, stream)
+
+    def encrypt_slots(self, scheme: int, slots, ct_ids, out, stream=None):
+        ps, ns, b = self._slots(slots)
+        _check(load_library().zinc_encrypt_slots(self.handle, scheme, ps, ns, b, _buf(ct_ids, "ct_ids", "int64", b),
+                                                 _buf(out, "out", "int64", b * self.ct_words), _stream(stream)))
         return out
 
     def bfv_encode(self, t: int, m, out, stream=None):
         """BFV plaintexts (int64 [batch][N] in Z_t) -> Delta * m residues."""
-        _check(load_library().zinc_bfv_encode(self.handle, int(t), _ptr(m), m.shape[0], _ptr(out), _stream(stream)))
+        b = _batch(m, "m")
+        _check(load_library().zinc_bfv_encode(self.handle, int(t), _buf(m, "m", "int64", b * self.n), b,
+                                              _buf(out, "out", "int64", b * self.pt_words), _stream(stream)))
         return out
 
     def bfv_decode(self, t: int, pt, out, stream=None):
         """Decrypted residues -> BFV plaintexts (int64, centred mod t)."""
-        _check(load_library().zinc_bfv_decode(self.handle, int(t), _ptr(pt), pt.shape[0], _ptr(out), _stream(stream)))
+        b = _batch(pt, "pt")
+        _check(load_library().zinc_bfv_decode(self.handle, int(t), _buf(pt, "pt", "int64", b * self.pt_words), b,
+                                              _buf(out, "out", "int64", b * self.n), _stream(stream)))
         return out
 
     def set_bgv(self, t: int):
@@ -303,58 +361,66 @@ class Context:
 
     def bgv_encode(self, m, out, stream=None):
         """BGV plaintexts (int64 [batch][N]) -> residues of m mod t."""
-        _check(load_library().zinc_bgv_encode(self.handle, _ptr(m), m.shape[0], _ptr(out), _stream(stream)))
+        b = _batch(m, "m")
+        _check(load_library().zinc_bgv_encode(self.handle, _buf(m, "m", "int64", b * self.n), b,
+                                              _buf(out, "out", "int64", b * self.pt_words), _stream(stream)))
         return out
 
     def bgv_decode(self, pt, out, stream=None):
         """Decrypted residues -> BGV plaintexts (int64, centred mod t)."""
-        _check(load_library().zinc_bgv_decode(self.handle, _ptr(pt), pt.shape[0], _ptr(out), _stream(stream)))
+        b = _batch(pt, "pt")
+        _check(load_library().zinc_bgv_decode(self.handle, _buf(pt, "pt", "int64", b * self.pt_words), b,
+                                              _buf(out, "out", "int64", b * self.n), _stream(stream)))
         return out
 
     def batch_encode(self, t: int, slots, out, stream=None):
         """Slot values (int64 [batch][N]) -> BFV/BGV plaintext coefficients in [0, t)."""
-        _check(load_library().zinc_batch_encode(self.handle, int(t), _ptr(slots), slots.shape[0], _ptr(out),
-                                                _stream(stream)))
+        b = _batch(slots, "slots")
+        _check(load_library().zinc_batch_encode(self.handle, int(t), _buf(slots, "slots", "int64", b * self.n), b,
+                                                _buf(out, "out", "int64", b * self.n), _stream(stream)))
         return out
 
     def batch_decode(self, t: int, m, out, stream=None):
         """Plaintext coefficients (int64 [batch][N]) -> slot values, centred mod t."""
-        _check(load_library().zinc_batch_decode(self.handle, int(t), _ptr(m), m.shape[0], _ptr(out),
-                                                _stream(stream)))
-        return out
-
-    def encrypt(self, pt, ct_ids, out, stream=None):
-        _check(load_library().zinc_encrypt(self.handle, _ptr(pt), pt.shape[0], _ptr(ct_ids), _ptr(out),
-                                           _stream(stream)))
-        return out
-
-    def encrypt_slots(self, scheme: int, slots, ct_ids, out, stream=None):
-        _check(load_library().zinc_encrypt_slots(self.handle, scheme, _ptr(slots), slots.shape[1],
-                                                 slots.shape[0], _ptr(ct_ids), _ptr(out), _stream(stream)))
+        b = _batch(m, "m")
+        _check(load_library().zinc_batch_decode(self.handle, int(t), _buf(m, "m", "int64", b * self.n), b,
+                                                _buf(out, "out", "int64", b * self.n), _stream(stream)))
         return out
 
     def decrypt(self, ct, out, stream=None):
-        _check(load_library().zinc_decrypt(self.handle, _ptr(ct), ct.shape[0], _ptr(out), _stream(stream)))
+        b = _batch(ct, "ct")
+        _check(load_library().zinc_decrypt(self.handle, _buf(ct, "ct", "int64", b * self.ct_words), b,
+                                           _buf(out, "out", "int64", b * self.pt_words), _stream(stream)))
         return out
 
     def decode(self, pt, out, stream=None):
-        _check(load_library().zinc_decode(self.handle, _ptr(pt), pt.shape[0], _ptr(out), _stream(stream)))
+        b = _batch(pt, "pt")
+        _check(load_library().zinc_decode(self.handle, _buf(pt, "pt", "int64", b * self.pt_words), b,
+                                          _buf(out, "out", "float64", b * (self.n // 2)), _stream(stream)))
         return out
 
-    def add(self, a, b, out, stream=None):
-        _check(load_library().zinc_add(self.handle, _ptr(a), _ptr(b), a.shape[0], _ptr(out), _stream(stream)))
+    def add(self, a, b_, out, stream=None):
+        b = _batch(a, "a")
+        w = b * self.ct_words
+        _check(load_library().zinc_add(self.handle, _buf(a, "a", "int64", w), _buf(b_, "b", "int64", w), b,
+                                       _buf(out, "out", "int64", w), _stream(stream)))
         return out
 
     def elementwise_zinc(self, hat, out, stream=None):
         """Algorithm 1's additions alone: out = hat + Enc(0) (NTT domain)."""
-        _check(load_library().zinc_elementwise_zinc(self.handle, _ptr(hat), hat.shape[0], _ptr(out),
-                                                    _stream(stream)))
+        b = _batch(hat, "hat")
+        w = b * self.ct_words
+        _check(load_library().zinc_elementwise_zinc(self.handle, _buf(hat, "hat", "int64", w), b,
+                                                    _buf(out, "out", "int64", w), _stream(stream)))
         return out
 
     def elementwise_vanilla(self, uhat, hat, out, stream=None):
         """Eq. 8's products and additions alone: out = pk * uhat + hat."""
-        _check(load_library().zinc_elementwise_vanilla(self.handle, _ptr(uhat), _ptr(hat), hat.shape[0],
-                                                       _ptr(out), _stream(stream)))
+        b = _batch(hat, "hat")
+        w = b * self.ct_words
+        _check(load_library().zinc_elementwise_vanilla(self.handle, _buf(uhat, "uhat", "int64", b * self.pt_words),
+                                                       _buf(hat, "hat", "int64", w), b,
+                                                       _buf(out, "out", "int64", w), _stream(stream)))
         return out
 
     def device_errors(self) -> int:
@@ -364,20 +430,28 @@ class Context:
 
     # -- kernel-level entry points -----------------------------------------
     def ntt_forward(self, limb: int, poly, stream=None):
-        _check(load_library().zinc_ntt_forward(self.handle, limb, _ptr(poly), poly.shape[0], _stream(stream)))
+        b = _batch(poly, "poly")
+        _check(load_library().zinc_ntt_forward(self.handle, limb, _buf(poly, "poly", "int64", b * self.n), b,
+                                               _stream(stream)))
         return poly
 
     def ntt_inverse(self, limb: int, poly, stream=None):
-        _check(load_library().zinc_ntt_inverse(self.handle, limb, _ptr(poly), poly.shape[0], _stream(stream)))
+        b = _batch(poly, "poly")
+        _check(load_library().zinc_ntt_inverse(self.handle, limb, _buf(poly, "poly", "int64", b * self.n), b,
+                                               _stream(stream)))
         return poly
 
     def sample(self, kind: int, tag: int, limb: int, ct_ids, out, stream=None):
-        _check(load_library().zinc_sample(self.handle, kind, tag, limb, _ptr(ct_ids), ct_ids.shape[0],
-                                          _ptr(out), _stream(stream)))
+        b = _batch(ct_ids, "ct_ids")
+        _check(load_library().zinc_sample(self.handle, kind, tag, limb, _buf(ct_ids, "ct_ids", "int64", b), b,
+                                          _buf(out, "out", "int64", b * self.n), _stream(stream)))
         return out
 
     def export_keys(self, sk=None, pk=None, zero=None, stream=None):
-        _check(load_library().zinc_export_keys(self.handle, _ptr(sk), _ptr(pk), _ptr(zero), _stream(stream)))
+        n = self.n
+        _check(load_library().zinc_export_keys(self.handle, _opt_buf(sk, "sk", "int64", self.M * n),
+                                               _opt_buf(pk, "pk", "int64", 2 * self.M * n),
+                                               _opt_buf(zero, "zero", "int64", self.ct_words), _stream(stream)))
 
 
 class Plan:
@@ -395,7 +469,13 @@ class Plan:
         self._ctxs = list(ctxs)
 
     def launch(self, slots, ct, stream=None):
-        _check(load_library().zinc_plan_launch(self.handle, _ptr(slots), _ptr(ct), _stream(stream)))
+        """Encrypt every item: `slots` is the float64 slot buffer and `ct` the
+        int64 output buffer the items' offsets index (the library checks that
+        both reach every item); None for both on an empty plan."""
+        ps = _opt_buf(slots, "slots", "float64", 0)
+        pc = _opt_buf(ct, "ct", "int64", 0)
+        _check(load_library().zinc_plan_launch(self.handle, ps, 0 if slots is None else slots.numel(), pc,
+                                               0 if ct is None else ct.numel(), _stream(stream)))
 
     def close(self):
         if getattr(self, "handle", None):
@@ -409,21 +489,23 @@ class Plan:
             pass
 
 
-def _server_config(scheme, n_streams, max_batch, hbm_budget, slots, ct):
-    return zinc_server_config(int(scheme), int(n_streams), int(max_batch), 0, int(hbm_budget), _ptr(slots),
-                              _ptr(ct) if ct is not None else None)
+def _server_config(scheme, n_streams, max_batch, hbm_budget, slots, ct, retain_outputs=False):
+    return zinc_server_config(int(scheme), int(n_streams), int(max_batch), int(bool(retain_outputs)),
+                              int(hbm_budget), _buf(slots, "slots", "float64", 1),
+                              _opt_buf(ct, "ct", "int64", 1), slots.numel(), 0 if ct is None else ct.numel())
 
 
 class Server:
     """Admission and continuous batching over resident contexts (zinc_server_*).
     `slots` is the base of every request's slot vectors; `ct` the base of their
-    outputs, or None for the server's own arena (outputs discarded)."""
+    outputs, or None for the server's own arena, where outputs are discarded on
+    completion or, with retain_outputs, kept until release()."""
 
     def __init__(self, ctxs, scheme: int, slots, ct=None, n_streams: int = 4, max_batch: int = 512,
-                 hbm_budget: int = 8 << 30):
+                 hbm_budget: int = 8 << 30, retain_outputs: bool = False):
         lib = load_library()
         arr = (_vp * len(ctxs))(*[c.handle for c in ctxs])
-        cfg = _server_config(scheme, n_streams, max_batch, hbm_budget, slots, ct)
+        cfg = _server_config(scheme, n_streams, max_batch, hbm_budget, slots, ct, retain_outputs)
         h = _vp()
         _check(lib.zinc_server_create(arr, len(ctxs), ctypes.byref(cfg), ctypes.byref(h)))
         self.handle = h.value
@@ -448,6 +530,22 @@ class Server:
         if not done.value:
             return None
         return {name: getattr(t, name) for name, _ in zinc_request_times._fields_}
+
+    def output_ptr(self, ticket: int) -> int:
+        """Device address of a completed request's retained ciphertexts."""
+        p = _vp()
+        _check(load_library().zinc_server_output(self.handle, int(ticket), ctypes.byref(p)))
+        return int(p.value)
+
+    def read_output(self, ticket: int, out, stream=None):
+        """Copy a completed request's retained ciphertexts (n_pt * 2 * L * N
+        uint64 words) into the int64 tensor `out`, on `stream`."""
+        _check(load_library().zinc_server_read_output(self.handle, int(ticket), _buf(out, "out", "int64", 1),
+                                                      out.numel(), _stream(stream)))
+        return out
+
+    def release(self, ticket: int):
+        _check(load_library().zinc_server_release(self.handle, int(ticket)))
 
     def drain(self):
         _check(load_library().zinc_server_drain(self.handle))

@@ -295,7 +295,7 @@ zinc_status zinc_precompute(zinc_ctx* c, void* stream) {
     if (e == hipSuccess) e = hipMemcpyAsync(tmp + words - 1, &id, 8, hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
         e = launch_encrypt_pt(c->dev, ZINC_SCHEME_VANILLA, tmp, 1, tmp + words - 1,
-                              const_cast<uint64_t*>(c->dev.zero), s);
+                              const_cast<uint64_t*>(c->dev.zero), s, true);
     hipError_t e2 = hipStreamSynchronize(s);
     (void)hipFree(tmp);
     if (e != hipSuccess) return hip_fail(e, "zinc_precompute");

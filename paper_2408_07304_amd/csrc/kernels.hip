@@ -22,10 +22,12 @@ k_encrypt(DevParams p, EncArgs a) {
     __shared__ u64 tab[kCdtTab];
     const uint32_t t = threadIdx.x;
     const uint32_t b = blockIdx.x;
+    const u64 id = a.ct_ids[b];
+    if (reserved_id(p, a, id, t)) return;
     load_cdt(tab, p.cdt, t);
     const uint32_t L = p.L;
     encrypt_item<LOGN, SCHEME, FROM_SLOTS, BGV>(p, a.slots + (size_t)b * a.n_slots, a.n_slots,
-                                          a.pt + (size_t)b * L * N, a.ct_ids[b], a.ct + (size_t)b * 2 * L * N,
+                                          a.pt + (size_t)b * L * N, id, a.ct + (size_t)b * 2 * L * N,
                                           lds, tab, t);
 }
 
@@ -270,9 +272,10 @@ hipError_t launch_keygen(const DevParams& p, uint64_t* sk, uint64_t* sk_sh, uint
 }
 
 hipError_t launch_encrypt_pt(const DevParams& p, int scheme, const uint64_t* pt, uint32_t batch,
-                             const uint64_t* ct_ids, uint64_t* ct, hipStream_t s) {
-    if (p.log_n == 15) return launch_split_encrypt(p, scheme, false, nullptr, 0, pt, batch, ct_ids, ct, s);
-    EncArgs a{nullptr, 0, (const u64*)pt, (const u64*)ct_ids, (u64*)ct};
+                             const uint64_t* ct_ids, uint64_t* ct, hipStream_t s, bool reserved_ok) {
+    if (p.log_n == 15)
+        return launch_split_encrypt(p, scheme, false, nullptr, 0, pt, batch, ct_ids, ct, s, reserved_ok);
+    EncArgs a{nullptr, 0, (const u64*)pt, (const u64*)ct_ids, (u64*)ct, reserved_ok ? 1u : 0u};
     const bool bgv = p.noise_t > 1;
 #define G_(LN, SCH, B) \
     hipLaunchKernelGGL((k_encrypt<LN, SCH, false, B>), dim3(batch), dim3(Cfg<LN>::G::T), 0, s, p, a)

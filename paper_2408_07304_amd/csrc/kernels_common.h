@@ -21,7 +21,19 @@ struct EncArgs {
     const u64* pt;           // [batch][L][N]   (!FROM_SLOTS)
     const u64* ct_ids;       // [batch]
     u64* ct;                 // [batch][2][L][N]
+    uint32_t reserved_ok;    // 1 only for the cached Enc(0), which uses ZINC_ZERO_ID
 };
+
+// Identifiers of 2^63 and above are reserved for the keys and the cached
+// Enc(0), whose randomness they select.  A direct encryption call naming one
+// writes nothing for that ciphertext and sets bit 2 of the error flags.  The
+// id is the same for every thread of the workgroup, so the whole group leaves
+// before its first barrier.
+__device__ __forceinline__ bool reserved_id(const DevParams& p, const EncArgs& a, u64 id, uint32_t t) {
+    if (a.reserved_ok || (id >> 63) == 0) return false;
+    if (t == 0) atomicOr(p.err, 4u);
+    return true;
+}
 
 // Per-limb view of the arithmetic: the forward NTT runs either on uint64
 // residues (Shoup, any modulus) or on doubles holding exact integers (moduli

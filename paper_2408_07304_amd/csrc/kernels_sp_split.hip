@@ -35,6 +35,8 @@ k_encrypt_sp_split(DevParams p, EncArgs a, long long* ws_all) {
     __shared__ u64 lds[LdsWords<NH>::value];
     __shared__ u64 tab[kCdtTab];
     const uint32_t t = threadIdx.x, b = blockIdx.x;
+    const u64 ct_id = a.ct_ids[b];
+    if (reserved_id(p, a, ct_id, t)) return;
     load_cdt(tab, p.cdt, t);
     const uint32_t L = p.L, M = p.M;
     long long* wm = ws_all + (size_t)b * 3 * NF;
@@ -42,7 +44,6 @@ k_encrypt_sp_split(DevParams p, EncArgs a, long long* ws_all) {
     long long* wd2 = wm + 2 * NF;
     u64* ct = a.ct + (size_t)b * 2 * L * NF;
     const u64* pt = FROM_SLOTS ? nullptr : a.pt + (size_t)b * L * NF;
-    const u64 ct_id = a.ct_ids[b];
 
     if constexpr (FROM_SLOTS) {
         long long mlo[RS], mhi[RS];

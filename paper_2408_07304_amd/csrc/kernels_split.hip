@@ -19,10 +19,12 @@ k_encrypt_split(DevParams p, EncArgs a) {
     __shared__ u64 lds[LdsWords<NH>::value];
     __shared__ u64 tab[kCdtTab];
     const uint32_t t = threadIdx.x, b = blockIdx.x;
+    const u64 id = a.ct_ids[b];
+    if (reserved_id(p, a, id, t)) return;
     load_cdt(tab, p.cdt, t);
     const uint32_t L = p.L;
     encrypt_item_split<SCHEME, FROM_SLOTS, BGV>(p, a.slots + (size_t)b * a.n_slots, a.n_slots, a.pt + (size_t)b * L * NF,
-                                           a.ct_ids[b], a.ct + (size_t)b * 2 * L * NF, lds, tab, t);
+                                           id, a.ct + (size_t)b * 2 * L * NF, lds, tab, t);
 }
 
 // ---------------------------------------------------------------------------
@@ -210,8 +212,8 @@ hipError_t launch_split_keygen(const DevParams& p, uint64_t* sk, uint64_t* sk_sh
 
 hipError_t launch_split_encrypt(const DevParams& p, int scheme, bool from_slots, const double* slots,
                                 uint32_t n_slots, const uint64_t* pt, uint32_t batch, const uint64_t* ct_ids,
-                                uint64_t* ct, hipStream_t s) {
-    EncArgs a{slots, n_slots, (const u64*)pt, (const u64*)ct_ids, (u64*)ct};
+                                uint64_t* ct, hipStream_t s, bool reserved_ok) {
+    EncArgs a{slots, n_slots, (const u64*)pt, (const u64*)ct_ids, (u64*)ct, reserved_ok ? 1u : 0u};
     if (p.noise_t > 1) {            // BGV: integer plaintexts only
         if (from_slots) return hipErrorInvalidValue;
         if (scheme == ZINC_SCHEME_ZINC)

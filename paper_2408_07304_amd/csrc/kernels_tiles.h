@@ -21,8 +21,10 @@ k_encrypt_tile(DevParams p, EncArgs a) {
     __shared__ u64 tab[kCdtTab];
     const uint32_t t = threadIdx.x;
     const uint32_t b = blockIdx.x;
+    const u64 id = a.ct_ids[b];
+    if (reserved_id(p, a, id, t)) return;
     load_cdt(tab, p.cdt, t);
-    encrypt_item_g<G, SCHEME, true, REG>(p, a.slots + (size_t)b * a.n_slots, a.n_slots, nullptr, a.ct_ids[b],
+    encrypt_item_g<G, SCHEME, true, REG>(p, a.slots + (size_t)b * a.n_slots, a.n_slots, nullptr, id,
                                     a.ct + (size_t)b * 2 * p.L * N, lds, tab, t);
 }
 

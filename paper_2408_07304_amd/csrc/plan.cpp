@@ -15,6 +15,8 @@ struct zinc_plan {
     void* d_block = nullptr;            // contexts, items, units, counter, dummy outputs
     zinc::PlanDev dev{};
     size_t n_items = 0;
+    uint64_t need_slots = 0;            // float64 words of slots the items read
+    uint64_t need_ct = 0;               // uint64 words of output the items write
     // captured graph and what it was captured with
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -104,9 +106,16 @@ zinc_status zinc_plan_create(zinc_ctx* const* ctxs, uint32_t n_ctx, const zinc_i
         if (scheme == ZINC_SCHEME_ZINC && !ctxs[c]->precomputed)
             return plan_fail(ZINC_E_STATE, "zinc_plan_create: context without a cached Enc(0)");
     }
+    uint64_t need_slots = 0, need_ct = 0;
     for (uint32_t i = 0; i < n_items; ++i) {
         if (items[i].ctx_idx >= n_ctx) return plan_fail(ZINC_E_INVAL, "zinc_plan_create: item context out of range");
         if (items[i].ct_id >= (1ull << 63)) return plan_fail(ZINC_E_INVAL, "zinc_plan_create: ct_id must be < 2^63");
+        const zinc_ctx* cx = ctxs[items[i].ctx_idx];
+        const uint64_t sw = cx->n / 2, cw = 2ull * cx->L * cx->n;
+        if (items[i].slot_off > ~0ull - sw || items[i].ct_off > ~0ull - cw)
+            return plan_fail(ZINC_E_INVAL, "zinc_plan_create: item offset out of range");
+        need_slots = std::max(need_slots, items[i].slot_off + sw);
+        need_ct = std::max(need_ct, items[i].ct_off + cw);
     }
     std::vector<PlanItem> dev_items;
     std::vector<PlanUnit> units;
@@ -116,6 +125,8 @@ zinc_status zinc_plan_create(zinc_ctx* const* ctxs, uint32_t n_ctx, const zinc_i
     p->ctxs.assign(ctxs, ctxs + n_ctx);
     p->scheme = scheme;
     p->n_items = n_items;
+    p->need_slots = need_slots;
+    p->need_ct = need_ct;
     auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
     const size_t b_ctx = al(sizeof(DevParams) * n_ctx), b_items = al(sizeof(PlanItem) * std::max<size_t>(1, dev_items.size()));
     const size_t b_units = al(sizeof(PlanUnit) * std::max<size_t>(1, units.size())), b_cnt = 256;
@@ -151,10 +162,19 @@ zinc_status zinc_plan_create(zinc_ctx* const* ctxs, uint32_t n_ctx, const zinc_i
     return ZINC_OK;
 }
 
-zinc_status zinc_plan_launch(zinc_plan* p, const double* slots, uint64_t* ct, void* stream) {
+zinc_status zinc_plan_launch(zinc_plan* p, const double* slots, uint64_t n_slot_words, uint64_t* ct,
+                             uint64_t n_ct_words, void* stream) {
     if (!p) return plan_fail(ZINC_E_INVAL, "zinc_plan_launch: null plan");
     if (p->n_items == 0) return ZINC_OK;
     if (!slots || !ct) return plan_fail(ZINC_E_INVAL, "zinc_plan_launch: null buffer");
+    if (n_slot_words < p->need_slots)
+        return plan_fail(ZINC_E_INVAL, "zinc_plan_launch: the slot buffer ends before an item's slots (" +
+                                           std::to_string(n_slot_words) + " < " + std::to_string(p->need_slots) +
+                                           " words)");
+    if (n_ct_words < p->need_ct)
+        return plan_fail(ZINC_E_INVAL, "zinc_plan_launch: the ciphertext buffer ends before an item's output (" +
+                                           std::to_string(n_ct_words) + " < " + std::to_string(p->need_ct) +
+                                           " words)");
     hipStream_t s = (hipStream_t)stream;
     if (!p->exec || p->cap_slots != slots || p->cap_ct != ct) {
         // Record the launch sequence on the plan's own stream (the caller's may

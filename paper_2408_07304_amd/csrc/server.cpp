@@ -37,11 +37,14 @@ struct Req {
     uint64_t bytes = 0;       // ciphertext bytes of the request
     uint64_t arena_off = 0;   // granted byte offset in the arena
     ReqState state = ReqState::Waiting;
+    bool held = false;        // completed, output kept in the arena until released
 };
 
 struct Lane {                 // one stream and the buffers of the batch it runs
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
+    hipEvent_t start = nullptr;    // timing events around the batch, for device times
+    hipEvent_t end = nullptr;
     PlanItem* h_items = nullptr;   // pinned staging of the batch's tables
     PlanUnit* h_units = nullptr;
     PlanDev dev{};                 // device tables of the batch
@@ -70,6 +73,8 @@ struct zinc_server {
     std::vector<PlanItem> dev_items;
     std::vector<PlanUnit> units;
 
+    hipEvent_t ref = nullptr;      // recorded (and complete) at creation: origin of device times
+
     uint64_t now() const { return now_ns() - t0; }
 };
 
@@ -79,10 +84,13 @@ zinc_status release_all(zinc_server* s) {
     for (auto& l : s->lanes) {
         if (l.stream) (void)hipStreamSynchronize(l.stream);
         if (l.done) (void)hipEventDestroy(l.done);
+        if (l.start) (void)hipEventDestroy(l.start);
+        if (l.end) (void)hipEventDestroy(l.end);
         if (l.stream) (void)hipStreamDestroy(l.stream);
         if (l.h_items) (void)hipHostFree(l.h_items);
         if (l.h_units) (void)hipHostFree(l.h_units);
     }
+    if (s->ref) (void)hipEventDestroy(s->ref);
     if (s->d_arena) (void)hipFree(s->d_arena);
     if (s->d_block) (void)hipFree(s->d_block);
     delete s;
@@ -102,11 +110,20 @@ zinc_status reap(zinc_server* s, uint32_t* n_done) {
         if (e == hipErrorNotReady) continue;
         if (e != hipSuccess) return hip_error(e, "zinc_server_progress: batch failed");
         const uint64_t t = s->now();
+        // device interval of the batch: its start and end events (both
+        // complete once `done` is) against the creation-time reference
+        float ms0 = 0.f, ms1 = 0.f;
+        if (hipEventElapsedTime(&ms0, s->ref, l.start) != hipSuccess ||
+            hipEventElapsedTime(&ms1, s->ref, l.end) != hipSuccess)
+            return plan_fail(ZINC_E_HIP, "zinc_server_progress: device timing events");
         for (uint64_t tk : l.tickets) {
             Req& q = s->reqs[tk];
             q.t.done_ns = t;
+            q.t.dev_start_ns = (uint64_t)((double)ms0 * 1e6);
+            q.t.dev_end_ns = (uint64_t)((double)ms1 * 1e6);
             q.state = ReqState::Done;
-            s->arena.release(q.arena_off, q.bytes);
+            if (s->cfg.retain_outputs) q.held = true;     // released by zinc_server_release
+            else s->arena.release(q.arena_off, q.bytes);
         }
         if (n_done) *n_done += (uint32_t)l.tickets.size();
         s->outstanding -= l.tickets.size();
@@ -164,7 +181,9 @@ zinc_status launch(zinc_server* s, uint32_t lane_idx) {
         e = hipMemcpyAsync((void*)d.units, l.h_units, sizeof(PlanUnit) * s->units.size(), hipMemcpyHostToDevice,
                            l.stream);
     uint64_t* out = s->cfg.d_ct ? s->cfg.d_ct : (uint64_t*)s->d_arena;
+    if (e == hipSuccess) e = hipEventRecord(l.start, l.stream);
     if (e == hipSuccess) e = launch_plan(d, s->cfg.scheme, s->cfg.d_slots, out, l.stream);
+    if (e == hipSuccess) e = hipEventRecord(l.end, l.stream);
     if (e == hipSuccess) e = hipEventRecord(l.done, l.stream);
     if (e != hipSuccess) return hip_error(e, "zinc_server_progress: batch launch");
     const uint64_t t = s->now();
@@ -195,7 +214,10 @@ zinc_status zinc_server_create(zinc_ctx* const* ctxs, uint32_t n_ctx, const zinc
         return plan_fail(ZINC_E_INVAL, "zinc_server_create: n_streams must be in [1, 16]");
     if (cfg->max_batch < 1 || cfg->max_batch > kMaxBatch)
         return plan_fail(ZINC_E_INVAL, "zinc_server_create: max_batch must be in [1, 65536]");
-    if (!cfg->d_slots) return plan_fail(ZINC_E_INVAL, "zinc_server_create: null slot buffer");
+    if (!cfg->d_slots || cfg->slots_len == 0) return plan_fail(ZINC_E_INVAL, "zinc_server_create: null slot buffer");
+    if (cfg->d_ct && cfg->ct_len == 0) return plan_fail(ZINC_E_INVAL, "zinc_server_create: empty output buffer");
+    if (cfg->retain_outputs > 1 || (cfg->retain_outputs && cfg->d_ct))
+        return plan_fail(ZINC_E_INVAL, "zinc_server_create: retain_outputs is 0 or 1, and 1 needs the arena (d_ct NULL)");
     for (uint32_t c = 0; c < n_ctx; ++c) {
         if (!ctxs[c]) return plan_fail(ZINC_E_INVAL, "zinc_server_create: null context");
         if (!ctxs[c]->keyed) return plan_fail(ZINC_E_STATE, "zinc_server_create: context without keys");
@@ -257,12 +279,21 @@ zinc_status zinc_server_create(zinc_ctx* const* ctxs, uint32_t n_ctx, const zinc
         l.dev.dummy = reinterpret_cast<uint64_t*>(lb + b_items + b_units + b_cnt);
         e = hipStreamCreateWithFlags(&l.stream, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&l.done, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreate(&l.start);
+        if (e == hipSuccess) e = hipEventCreate(&l.end);
         if (e == hipSuccess) e = hipHostMalloc((void**)&l.h_items, sizeof(PlanItem) * s->item_cap, hipHostMallocDefault);
         if (e == hipSuccess) e = hipHostMalloc((void**)&l.h_units, sizeof(PlanUnit) * s->unit_cap, hipHostMallocDefault);
         if (e != hipSuccess) {
             release_all(s);
             return hip_error(e, "zinc_server_create: stream resources");
         }
+    }
+    e = hipEventCreate(&s->ref);
+    if (e == hipSuccess) e = hipEventRecord(s->ref, s->lanes[0].stream);
+    if (e == hipSuccess) e = hipEventSynchronize(s->ref);
+    if (e != hipSuccess) {
+        release_all(s);
+        return hip_error(e, "zinc_server_create: reference event");
     }
     s->t0 = now_ns();
     *out = s;
@@ -277,11 +308,16 @@ zinc_status zinc_server_submit(zinc_server* s, const zinc_request* r, uint64_t* 
     if (r->ct_id >= (1ull << 63) || r->n_pt > (1ull << 63) - r->ct_id)
         return plan_fail(ZINC_E_INVAL, "zinc_server_submit: ct_id + n_pt must be <= 2^63");
     const zinc_ctx* c = s->ctxs[r->ctx_idx];
+    const uint64_t slot_words = (uint64_t)r->n_pt * (c->n / 2), ct_words = (uint64_t)r->n_pt * 2ull * c->L * c->n;
     Req q;
     q.r = *r;
-    q.bytes = (uint64_t)r->n_pt * 2ull * c->L * c->n * 8ull;
+    q.bytes = ct_words * 8ull;
     if (((q.bytes + kAlign - 1) & ~(kAlign - 1)) > s->arena.size())
         return plan_fail(ZINC_E_RANGE, "zinc_server_submit: request output exceeds the HBM budget");
+    if (r->slot_off > s->cfg.slots_len || slot_words > s->cfg.slots_len - r->slot_off)
+        return plan_fail(ZINC_E_INVAL, "zinc_server_submit: the request's slots end beyond slots_len");
+    if (s->cfg.d_ct && (r->ct_off > s->cfg.ct_len || ct_words > s->cfg.ct_len - r->ct_off))
+        return plan_fail(ZINC_E_INVAL, "zinc_server_submit: the request's ciphertexts end beyond ct_len");
     std::memset(&q.t, 0, sizeof(q.t));
     q.t.submit_ns = s->now();
     const uint64_t tk = s->reqs.size();
@@ -315,11 +351,52 @@ zinc_status zinc_server_query(zinc_server* s, uint64_t ticket, int* done, zinc_r
     return ZINC_OK;
 }
 
+zinc_status zinc_server_output(zinc_server* s, uint64_t ticket, uint64_t** d_out) {
+    if (!s || !d_out) return plan_fail(ZINC_E_INVAL, "zinc_server_output: null argument");
+    *d_out = nullptr;
+    if (!s->cfg.retain_outputs) return plan_fail(ZINC_E_STATE, "zinc_server_output: the server does not retain outputs");
+    if (ticket >= s->reqs.size()) return plan_fail(ZINC_E_INVAL, "zinc_server_output: unknown ticket");
+    const Req& q = s->reqs[ticket];
+    if (q.state != ReqState::Done || !q.held)
+        return plan_fail(ZINC_E_STATE, "zinc_server_output: the request has not completed or was released");
+    *d_out = reinterpret_cast<uint64_t*>(static_cast<char*>(s->d_arena) + q.arena_off);
+    return ZINC_OK;
+}
+
+zinc_status zinc_server_read_output(zinc_server* s, uint64_t ticket, uint64_t* d_dst, uint64_t dst_words,
+                                    void* stream) {
+    uint64_t* src = nullptr;
+    if (!d_dst) return plan_fail(ZINC_E_INVAL, "zinc_server_read_output: null destination");
+    if (zinc_status st = zinc_server_output(s, ticket, &src)) return st;
+    const Req& q = s->reqs[ticket];
+    if (dst_words < q.bytes / 8)
+        return plan_fail(ZINC_E_INVAL, "zinc_server_read_output: the destination is shorter than the request's output");
+    const hipError_t e = hipMemcpyAsync(d_dst, src, q.bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_error(e, "zinc_server_read_output");
+    return ZINC_OK;
+}
+
+zinc_status zinc_server_release(zinc_server* s, uint64_t ticket) {
+    if (!s) return plan_fail(ZINC_E_INVAL, "zinc_server_release: null server");
+    if (!s->cfg.retain_outputs) return plan_fail(ZINC_E_STATE, "zinc_server_release: the server does not retain outputs");
+    if (ticket >= s->reqs.size()) return plan_fail(ZINC_E_INVAL, "zinc_server_release: unknown ticket");
+    Req& q = s->reqs[ticket];
+    if (q.state != ReqState::Done || !q.held)
+        return plan_fail(ZINC_E_STATE, "zinc_server_release: the request has not completed or was released");
+    q.held = false;
+    s->arena.release(q.arena_off, q.bytes);
+    return ZINC_OK;
+}
+
 zinc_status zinc_server_drain(zinc_server* s) {
     if (!s) return plan_fail(ZINC_E_INVAL, "zinc_server_drain: null server");
     while (s->outstanding) {
         zinc_status st = zinc_server_progress(s, nullptr);
         if (st != ZINC_OK) return st;
+        bool running = false;
+        for (const Lane& l : s->lanes) running |= l.busy;
+        if (!running && s->admitted.empty() && !s->waiting.empty())   // only held outputs can free the arena
+            return plan_fail(ZINC_E_STATE, "zinc_server_drain: waiting requests need retained outputs to be released");
     }
     return ZINC_OK;
 }
@@ -333,6 +410,8 @@ zinc_status zinc_serve_trace(zinc_ctx* const* ctxs, uint32_t n_ctx, const zinc_s
                              const zinc_request* reqs, const uint64_t* arrival_ns, uint32_t n_req,
                              zinc_request_times* times) {
     if ((!reqs || !arrival_ns || !times) && n_req) return plan_fail(ZINC_E_INVAL, "zinc_serve_trace: null argument");
+    if (cfg && cfg->retain_outputs)
+        return plan_fail(ZINC_E_INVAL, "zinc_serve_trace: a replay releases outputs as requests complete (retain_outputs 0)");
     for (uint32_t i = 1; i < n_req; ++i)
         if (arrival_ns[i] < arrival_ns[i - 1])
             return plan_fail(ZINC_E_INVAL, "zinc_serve_trace: arrivals must be non-decreasing");

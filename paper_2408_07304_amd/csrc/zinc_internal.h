@@ -166,8 +166,9 @@ void set_error(const std::string& msg);
 // kernel launchers (return hipError_t of the launch)
 hipError_t launch_keygen(const DevParams& p, uint64_t* sk, uint64_t* sk_sh, uint64_t* pk,
                          uint64_t* pk_sh, hipStream_t s);
+// reserved_ok: the identifiers may be reserved ones (the cached Enc(0) only)
 hipError_t launch_encrypt_pt(const DevParams& p, int scheme, const uint64_t* pt, uint32_t batch,
-                             const uint64_t* ct_ids, uint64_t* ct, hipStream_t s);
+                             const uint64_t* ct_ids, uint64_t* ct, hipStream_t s, bool reserved_ok = false);
 hipError_t launch_encrypt_slots(const DevParams& p, int scheme, const double* slots,
                                 uint32_t n_slots, uint32_t batch, const uint64_t* ct_ids,
                                 uint64_t* ct, hipStream_t s);
@@ -234,7 +235,7 @@ hipError_t launch_split_keygen(const DevParams& p, uint64_t* sk, uint64_t* sk_sh
                                uint64_t* pk_sh, hipStream_t s);
 hipError_t launch_split_encrypt(const DevParams& p, int scheme, bool from_slots, const double* slots,
                                 uint32_t n_slots, const uint64_t* pt, uint32_t batch,
-                                const uint64_t* ct_ids, uint64_t* ct, hipStream_t s);
+                                const uint64_t* ct_ids, uint64_t* ct, hipStream_t s, bool reserved_ok = false);
 hipError_t launch_split_encode(const DevParams& p, const double* slots, uint32_t n_slots,
                                uint32_t batch, uint64_t* pt, hipStream_t s);
 hipError_t launch_split_decrypt(const DevParams& p, const uint64_t* ct, uint32_t batch,

@@ -1,7 +1,9 @@
 """Edge cases of the batch entry points: empty batches (every entry point, and
 a plan with no items) are no-ops; messages whose coefficients exceed 2^52 take
 the integer route of the fused kernel and still equal encode-then-encrypt;
-the largest allowed ciphertext identifier is bit-exact against the oracle."""
+the largest allowed ciphertext identifier is bit-exact against the oracle;
+reserved identifiers (2^63 and above) are refused by every encryption
+entry point without touching their ciphertexts."""
 import numpy as np
 import pytest
 
@@ -75,10 +77,9 @@ def test_large_messages_take_the_integer_route(scheme):
     got = from_dev(pt)
     m, _ = oracle.encode(P, z[0])
     assert np.abs(m).max() > 2 ** 52
-    # each coefficient is the oracle's integer within the FP64 evaluation
-    # error at this size (the same bound as the tie window of the encoding
-    # parity test: 8 log2(N) 2^-53 max|x|, about 190 here), and the same
-    # integer on every limb
+    # each coefficient is the oracle's integer within a worst-case bound on
+    # the FP64 evaluation error at this size, 8 log2(N) 2^-53 max|x| (about
+    # 190 here), and the same integer on every limb
     bound = 8 * np.log2(P.n) * 2.0 ** -53 * float(np.abs(m).max()) + 1
     deltas = []
     for l, q in enumerate(P.data_moduli):
@@ -107,3 +108,46 @@ def test_largest_ct_id_bit_exact():
             want = (oracle.encrypt_zinc(P, zero, pt[i], cid) if scheme == zinc.ZINC_SCHEME_ZINC
                     else oracle.encrypt_vanilla(P, pk, pt[i], cid))
             assert np.array_equal(got[i], want), (scheme, cid)
+
+
+@pytest.mark.parametrize("name", ["n4096", "n32768"])
+def test_reserved_identifiers_are_refused(name):
+    """An identifier of 2^63 or more (the keys' and the cached Enc(0)'s) in a
+    direct encryption call: that ciphertext is left unwritten and bit 2 of
+    the device error flags is set; the others in the batch are encrypted as
+    usual.  Every entry point, both ring-degree families (N = 32768 runs the
+    split kernels)."""
+    torch = torch_cuda()
+    c = gpu_ctx(name)
+    P = oracle_keys(name)[0]
+    rng = np.random.default_rng(33)
+    z = to_dev(rng.uniform(-1, 1, size=(3, P.n // 2)))
+    pt = empty_u64(3, P.L, P.n)
+    c.encode(z, pt)
+    idv = [5, zinc.ZINC_ZERO_ID, 1 << 63]
+    d_ids = ids(idv)
+    sentinel = -0x5A5A5A5A5A5A5A5B
+    assert c.device_errors() == 0
+    calls = [("slots vanilla", lambda o: c.encrypt_slots(zinc.ZINC_SCHEME_VANILLA, z, d_ids, o),
+              lambda o: c.encrypt_slots(zinc.ZINC_SCHEME_VANILLA, z[:1], d_ids[:1], o)),
+             ("slots zinc", lambda o: c.encrypt_slots(zinc.ZINC_SCHEME_ZINC, z, d_ids, o),
+              lambda o: c.encrypt_slots(zinc.ZINC_SCHEME_ZINC, z[:1], d_ids[:1], o)),
+             ("slots vanilla_sp", lambda o: c.encrypt_slots(zinc.ZINC_SCHEME_VANILLA_SP, z, d_ids, o),
+              lambda o: c.encrypt_slots(zinc.ZINC_SCHEME_VANILLA_SP, z[:1], d_ids[:1], o)),
+             ("encrypt", lambda o: c.encrypt(pt, d_ids, o), lambda o: c.encrypt(pt[:1], d_ids[:1], o)),
+             ("encrypt_vanilla", lambda o: c.encrypt_vanilla(pt, d_ids, o),
+              lambda o: c.encrypt_vanilla(pt[:1], d_ids[:1], o)),
+             ("encrypt_vanilla_sp", lambda o: c.encrypt_vanilla_sp(pt, d_ids, o),
+              lambda o: c.encrypt_vanilla_sp(pt[:1], d_ids[:1], o))]
+    for what, batch_call, one_call in calls:
+        out = torch.full((3, 2, P.L, P.n), sentinel, dtype=torch.int64, device="cuda")
+        say(f"{name} reserved identifiers: {what}")
+        batch_call(out)
+        assert c.device_errors() & 4, what
+        assert c.device_errors() == 0
+        got = from_dev(out)
+        assert np.all(got[1:].view(np.int64) == sentinel), what
+        one = empty_u64(1, 2, P.L, P.n)
+        one_call(one)
+        assert np.array_equal(got[0], from_dev(one)[0]), what
+        assert c.device_errors() == 0

@@ -105,6 +105,10 @@ def test_null_arguments_are_rejected(lib):
     assert lib.zinc_server_progress(None, None) == zinc.ZINC_E_INVAL
     assert lib.zinc_server_query(None, 0, None, None) == zinc.ZINC_E_INVAL
     assert lib.zinc_server_drain(None) == zinc.ZINC_E_INVAL
+    assert lib.zinc_server_output(None, 0, None) == zinc.ZINC_E_INVAL
+    assert lib.zinc_server_read_output(None, 0, None, 0, None) == zinc.ZINC_E_INVAL
+    assert lib.zinc_server_release(None, 0) == zinc.ZINC_E_INVAL
+    assert lib.zinc_plan_launch(None, None, 0, None, 0, None) == zinc.ZINC_E_INVAL
     assert lib.zinc_server_destroy(None) == zinc.ZINC_OK
     assert lib.zinc_serve_trace(None, 0, None, None, None, 0, None) == zinc.ZINC_E_INVAL
     assert lib.zinc_ctx_info(None, None) == zinc.ZINC_E_INVAL

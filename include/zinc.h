@@ -204,6 +204,20 @@ zinc_status zinc_decode(zinc_ctx* ctx, const uint64_t* d_pt, uint32_t batch, dou
 zinc_status zinc_encrypt_vanilla_sp(zinc_ctx* ctx, const uint64_t* d_pt, uint32_t batch,
                                     const uint64_t* d_ct_ids, uint64_t* d_ct, void* stream);
 
+/* zinc_encrypt_vanilla_sp without allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving loops that
+ * forbid it): same arguments and results, but the per-ciphertext scratch
+ * (3 * N int64) lives in a 64 MiB static device array of the library, one
+ * per GPU, held until the process ends.  So a call takes at most
+ * 64 MiB / (24 N) ciphertexts (682, 341, 170 and 85 at N = 4096 ... 32768;
+ * ZINC_E_RANGE above).  Calls on one GPU share that array: calls that
+ * overlap in time on one GPU (different streams, threads) race and must be
+ * serialised by the caller.  The scratch needs no clearing (each ciphertext's
+ * rows are written before they are read).  The context's device must be
+ * current (ZINC_E_HIP otherwise).  Calls no allocating routine. */
+zinc_status zinc_encrypt_vanilla_sp_noalloc(zinc_ctx* ctx, const uint64_t* d_pt, uint32_t batch,
+                                            const uint64_t* d_ct_ids, uint64_t* d_ct, void* stream);
+
 /* BFV on the same contexts (Scheme Flexibility section, Eq. 12): the message
  * is scaled by Delta = floor(Q / t), Q the product of the data moduli, and the
  * rest of the encryption is unchanged, so zinc_encrypt (Zinc) and

@@ -98,6 +98,7 @@ _SIGS = {
     "zinc_encrypt_vanilla": (ctypes.c_int, [_vp, _vp, _u32, _vp, _vp, _vp]),
     "zinc_encrypt": (ctypes.c_int, [_vp, _vp, _u32, _vp, _vp, _vp]),
     "zinc_encrypt_vanilla_sp": (ctypes.c_int, [_vp, _vp, _u32, _vp, _vp, _vp]),
+    "zinc_encrypt_vanilla_sp_noalloc": (ctypes.c_int, [_vp, _vp, _u32, _vp, _vp, _vp]),
     "zinc_bfv_encode": (ctypes.c_int, [_vp, ctypes.c_uint64, _vp, _u32, _vp, _vp]),
     "zinc_bfv_decode": (ctypes.c_int, [_vp, ctypes.c_uint64, _vp, _u32, _vp, _vp]),
     "zinc_set_bgv": (ctypes.c_int, [_vp, ctypes.c_uint64]),
@@ -331,6 +332,11 @@ class Context:
     def encrypt_vanilla_sp(self, pt, ct_ids, out, stream=None):
         """Vanilla with division by the special prime (a SEAL-style baseline)."""
         return self._encrypt_pt(load_library().zinc_encrypt_vanilla_sp, pt, ct_ids, out, stream)
+
+    def encrypt_vanilla_sp_noalloc(self, pt, ct_ids, out, stream=None):
+        """encrypt_vanilla_sp with the library's static scratch (no allocation;
+        calls overlapping on one GPU race)."""
+        return self._encrypt_pt(load_library().zinc_encrypt_vanilla_sp_noalloc, pt, ct_ids, out, stream)
 
     def encrypt(self, pt, ct_ids, out, stream=None):
         return self._encrypt_pt(load_library().zinc_encrypt, pt, ct_ids, out, stream)

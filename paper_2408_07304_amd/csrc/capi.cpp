@@ -388,6 +388,29 @@ zinc_status zinc_encrypt_vanilla_sp(zinc_ctx* c, const uint64_t* pt, uint32_t ba
     return encrypt_sp(c, false, nullptr, 0, pt, batch, ids, ct, stream);
 }
 
+// The same encryption with the scratch rows in the library's static device
+// array instead of stream-ordered allocations (callers that cannot allocate).
+zinc_status zinc_encrypt_vanilla_sp_noalloc(zinc_ctx* c, const uint64_t* pt, uint32_t batch, const uint64_t* ids,
+                                            uint64_t* ct, void* stream) {
+    if (!c) return fail(ZINC_E_INVAL, "zinc_encrypt_vanilla_sp_noalloc: null context");
+    if (!c->keyed) return fail(ZINC_E_STATE, "zinc_encrypt_vanilla_sp_noalloc before zinc_keygen");
+    if (c->dev.noise_t > 1) return fail(ZINC_E_STATE, "zinc_encrypt_vanilla_sp_noalloc: not built for BGV contexts");
+    if (zinc_status s = check_batch("zinc_encrypt_vanilla_sp_noalloc", batch, {pt, ids, ct})) return s;
+    if (batch == 0) return ZINC_OK;
+    const size_t per_ct = (size_t)3 * c->n * sizeof(int64_t);
+    if ((size_t)batch * per_ct > kSpScratchBytes)
+        return fail(ZINC_E_RANGE, "zinc_encrypt_vanilla_sp_noalloc: at most " +
+                                      std::to_string(kSpScratchBytes / per_ct) + " ciphertexts of ring degree " +
+                                      std::to_string(c->n) + " per call (" +
+                                      std::to_string(kSpScratchBytes >> 20) + " MiB of static scratch)");
+    long long* ws = nullptr;
+    const hipError_t e = sp_scratch(c->device, &ws);
+    if (e != hipSuccess) return hip_fail(e, "zinc_encrypt_vanilla_sp_noalloc: static scratch (is the context's device current?)");
+    return launched(launch_encrypt_sp(c->dev, false, nullptr, 0, pt, batch, ids, ct, reinterpret_cast<int64_t*>(ws),
+                                      (hipStream_t)stream),
+                    "special-prime vanilla launch");
+}
+
 // Constants of the BFV encoding / decoding for plaintext modulus t.
 static zinc_status bfv_consts(const zinc_ctx* c, uint64_t t, BfvConsts* k, const char* fn) {
     if (c->dev.noise_t > 1) return fail(ZINC_E_STATE, std::string(fn) + ": the context is in BGV form");

@@ -15,6 +15,8 @@
 // the encoded message, D_1, D_2 (pass-0 layout, each thread reads back what
 // it wrote).  NTT(u) mod p waits in the D_2 row (in the last pass's layout)
 // until D_2 overwrites it after the inverse transform's first barrier.
+#include <mutex>
+
 #include "kernels_common.h"
 
 namespace zinc {
@@ -180,6 +182,38 @@ hipError_t launch_encrypt_sp(const DevParams& p, bool from_slots, const double* 
     }
 #undef F
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free entry point (zinc_encrypt_vanilla_sp_noalloc):
+// a file-scope device array, one copy per GPU at its own address, held until
+// the process ends and shared by every call on that GPU.  On the host the
+// array's name only stands in for the device symbol, so host code uses the
+// address hipGetSymbolAddress gives for the current device, never the name.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) long long scratch[kSpScratchBytes / sizeof(long long)];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+long long* g_scratch[kMaxDevices] = {};
+}  // namespace
+
+hipError_t sp_scratch(int device, long long** out) {
+    *out = nullptr;
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device || device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[device]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch[device] = static_cast<long long*>(p);
+    }
+    *out = g_scratch[device];
+    return hipSuccess;
 }
 
 }  // namespace zinc

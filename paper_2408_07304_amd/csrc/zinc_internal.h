@@ -191,6 +191,11 @@ hipError_t launch_scale_pk(const DevParams& p, uint64_t* pkp, uint64_t* pkp_sh, 
 hipError_t launch_encrypt_sp(const DevParams& p, bool from_slots, const double* slots, uint32_t n_slots,
                              const uint64_t* pt, uint32_t batch, const uint64_t* ct_ids, uint64_t* ct, int64_t* ws,
                              hipStream_t s);
+// Static scratch of zinc_encrypt_vanilla_sp_noalloc: its size, and its device
+// address on `device`, which must be the current device (looked up once per
+// device; hipErrorInvalidDevice otherwise).
+constexpr size_t kSpScratchBytes = 64ull << 20;
+hipError_t sp_scratch(int device, long long** out);
 
 // BFV integer encoding / decoding (kernels_bfv.hip)
 hipError_t launch_bfv_encode(const DevParams& p, const BfvConsts& k, const int64_t* m, uint32_t batch, uint64_t* pt,

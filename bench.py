@@ -23,27 +23,48 @@ sys.path.insert(0, ROOT)
 METRIC = "CKKS encryptions/sec (Zinc vs vanilla, same GPU) at N=8192; p99 latency served"
 
 # ALU roofline of the NTT butterflies (the dominant work of the fused launch).
-# VALU issue rate of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.32e12
-# lane-cycles/s; integer multiplies (v_mad_u64_u32, v_mul_lo/hi_u32) and FP64
-# FMA all issue at the full rate on gfx950, so a butterfly costs its
-# instruction count.  The shortest butterfly per modulus class:
-#   q >= 2^50, 64-bit integer Cooley-Tukey with a Shoup twiddle and lazy
-#   (Harvey) reduction: 26 VALU ops (6 for hi64(y*w'), 4 + 4 for the two low
-#   64-bit products, 2 for their difference, 4 to subtract 2q from x when
-#   needed, 2 for x + t, 4 for x - t + 2q);
-#   q < 2^50, exact FP64 arithmetic: 8 VALU ops (mul + rint for the quotient,
-#   mul and FMA for the exact product, FMA for the remainder, add, and the
-#   butterfly's add and subtract).
-# The peak butterfly rate of a launch is the VALU rate over the mean cost of
-# its limbs' butterflies.
+# Measured peak: zinc_butterfly_rate runs the kernels' own butterfly in a
+# register-resident loop over a full-occupancy grid (no memory traffic) and
+# returns butterflies per second, per arithmetic: 64-bit integer Shoup with
+# the lazy reduction every fourth stage (moduli >= 2^50) or exact FP64
+# (moduli < 2^50).  A launch's limbs have equal butterfly counts, so its peak
+# is the harmonic mean of its limbs' rates.
+# Model beside it, from the chip's unit counts and clock: VALU issue of
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.32e12 lane-instructions/s over
+# the butterfly's instruction count in the gfx950 code (23.25 integer, 8 FP64;
+# one instruction per lane-cycle).
 VALU_LANE_CYCLES_PER_S = 256 * 4 * 16 * 2.4e9
-BFLY_COST_INT = 26
+BFLY_COST_INT = 23.25
 BFLY_COST_FP64 = 8
 
 
-def peak_bfly_per_s(limbs: int, fp64_mask: int) -> float:
+def model_peak_bfly_per_s(limbs: int, fp64_mask: int) -> float:
     cost = sum(BFLY_COST_FP64 if (fp64_mask >> l) & 1 else BFLY_COST_INT for l in range(limbs)) / limbs
     return VALU_LANE_CYCLES_PER_S / cost
+
+
+_RATES = {}
+
+
+def measured_rates(moduli, limbs: int, fp64_mask: int) -> list:
+    """Measured butterflies/s of each data limb's arithmetic (one measurement
+    per arithmetic, with the first such limb's modulus)."""
+    import paper_2408_07304_amd as zinc
+
+    out = []
+    for l in range(limbs):
+        arith = (fp64_mask >> l) & 1
+        if arith not in _RATES:
+            _RATES[arith] = (zinc.butterfly_rate(arith, moduli[l]), moduli[l])
+            print(f"[bench] butterfly rate ({'FP64' if arith else 'integer'}, q = {moduli[l]}): "
+                  f"{_RATES[arith][0] / 1e12:.3f} T/s", file=sys.stderr, flush=True)
+        out.append(_RATES[arith][0])
+    return out
+
+
+def measured_peak_bfly_per_s(moduli, limbs: int, fp64_mask: int) -> float:
+    rates = measured_rates(moduli, limbs, fp64_mask)
+    return limbs / sum(1.0 / r for r in rates)
 
 
 HBM_PEAK_BYTES_PER_S = 8.0e12
@@ -115,12 +136,24 @@ def elementwise_traffic(workload: str, scheme_name: str):
     return k["read_bytes_per_launch"] + k["write_bytes_per_launch"]
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (what lscpu reports), from /proc/cpuinfo."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(ws, scheme: int, budget_s: float):
     """The CPU oracle (plain C, -O2, scalar) on a bounded sample of the same
-    workload: encode + encrypt of the first plaintexts, one per thread."""
+    workload: encode + encrypt of the first plaintexts, one per thread, on all
+    host threads (up to 16) for most of the budget and on one thread for the
+    rest (the like-for-like analogue of the paper's single-threaded setup)."""
     import concurrent.futures as cf
-
-    import numpy as np
 
     import oracle
     from paper_2408_07304_amd.workloads import make_slots
@@ -134,15 +167,23 @@ def cpu_baseline(ws, scheme: int, budget_s: float):
     t0 = time.perf_counter()
     oracle.encrypt_slots(P, scheme, key, z1[0], 0)
     one = time.perf_counter() - t0
-    count = int(min(ws.batch, max(threads, threads * budget_s / max(one, 1e-6))))
+    count = int(min(ws.batch, max(threads, threads * 0.75 * budget_s / max(one, 1e-6))))
     z = make_slots(ws, count)
     t0 = time.perf_counter()
     with cf.ThreadPoolExecutor(max_workers=threads) as ex:
         list(ex.map(lambda i: oracle.encrypt_slots(P, scheme, key, z[i], i), range(count)))
     dt = time.perf_counter() - t0
+    count1 = int(max(1, min(count, 0.25 * budget_s / max(one, 1e-6))))
+    t0 = time.perf_counter()
+    for i in range(count1):
+        oracle.encrypt_slots(P, scheme, key, z[i], i)
+    dt1 = time.perf_counter() - t0
     return {"value": count / dt, "unit": "enc/s", "cores": threads, "kind": "oracle",
             "sample": f"{count} of {ws.batch} plaintexts of {ws.name} (encode + "
-                      f"{'Zinc' if scheme == 1 else 'vanilla'} encrypt), {threads} threads, {dt:.1f} s"}
+                      f"{'Zinc' if scheme == 1 else 'vanilla'} encrypt), {threads} threads, {dt:.1f} s; "
+                      f"{count1} of them on 1 thread, {dt1:.1f} s",
+            "one_thread": {"value": count1 / dt1, "unit": "enc/s", "cores": 1},
+            "cpu_model": cpu_model(), "host_threads": os.cpu_count()}
 
 
 _ORACLE_KEYS = {}
@@ -249,6 +290,58 @@ def bench_config_table(steps: int, warmup: int, budget_s: float) -> list:
         rows.append(row)
         print(f"[bench] config table: {row}", file=sys.stderr, flush=True)
     return rows
+
+
+def bench_configs(steps: int, warmup: int, tune_cache) -> dict:
+    """The other single-parameter configurations (N = 4096 with 64 plaintexts,
+    N = 16384 with 4096 plaintexts), both schemes: the autotuned fused launch,
+    timed with HIP events on the launch stream, with the measured-peak ALU
+    roofline of each."""
+    import torch
+
+    import paper_2408_07304_amd as zinc
+    from paper_2408_07304_amd.workloads import W_LARGE, W_SMALL, make_slots
+
+    out = {}
+    for ws in (W_SMALL, W_LARGE):
+        ps = ws.params[0]
+        ctx = zinc.context_for(ps)
+        ctx.keygen()
+        ctx.precompute()
+        ctx.autotune(batch=ws.batch, cache_path=tune_cache or None)
+        z = torch.from_numpy(make_slots(ws)).to("cuda")
+        ids = torch.arange(ws.batch, dtype=torch.int64, device="cuda")
+        ct = torch.empty((ws.batch, 2, ps.limbs, ps.n), dtype=torch.int64, device="cuda")
+        mask = ctx.info()["ntt_fp64_mask"]
+        peak = measured_peak_bfly_per_s(ctx.moduli, ps.limbs, mask)
+        r = {"N": ps.n, "batch": ws.batch, "data_limbs": ps.limbs, "slot_values": ws.dist,
+             "tuning": ctx.get_tuning()}
+        for name, sch in (("zinc", 1), ("vanilla", 0)):
+            settle(lambda: ctx.encrypt_slots(sch, z, ids, ct))
+            for _ in range(max(1, warmup)):
+                ctx.encrypt_slots(sch, z, ids, ct)
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(steps):
+                ctx.encrypt_slots(sch, z, ids, ct)
+            b.record()
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b) / steps
+            ach = ws.batch * butterflies(ps.n, ps.limbs, sch) / (ms / 1e3)
+            r[name] = {"kernel_ms": ms, "enc_per_s": ws.batch / (ms / 1e3), "alu_frac": ach / peak,
+                       "hbm_frac": ws.batch * algorithmic_bytes(ps.n, ps.limbs, ps.slots) / (ms / 1e3)
+                       / HBM_PEAK_BYTES_PER_S}
+        r["zinc_over_vanilla"] = r["vanilla"]["kernel_ms"] / r["zinc"]["kernel_ms"]
+        r["peak_gbutterfly_per_s"] = peak / 1e9
+        out[ws.name] = r
+        print(f"[bench] config {ws.name}: {r}", file=sys.stderr, flush=True)
+        if ctx.device_errors():
+            raise SystemExit("device error flag set during the benchmark")
+        del z, ct, ids
+        ctx.close()
+        torch.cuda.empty_cache()
+    return out
 
 
 def bench_encrypt_only(ctx, z, ids, ct, steps: int, warmup: int) -> dict:
@@ -482,6 +575,7 @@ def main():
     ap.add_argument("--tune-cache", default=TUNE_CACHE,
                     help="autotuning cache file ('' to time every candidate afresh)")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-degree plan and serving measurements")
+    ap.add_argument("--no-configs", action="store_true", help="skip the N = 4096 and N = 16384 configurations")
     ap.add_argument("--serve-requests", type=int, default=10000, help="measured requests of the serving replay")
     ap.add_argument("--serve-warmup", type=int, default=500)
     ap.add_argument("--serve-streams", type=int, default=4)
@@ -563,7 +657,9 @@ def main():
     value = ws.batch / (r["ms_per_step"] / 1e3)
     bfly = ws.batch * butterflies(ps.n, ps.limbs, sch)
     achieved = bfly / (r["kernel_ms"] / 1e3)
-    peak = peak_bfly_per_s(ps.limbs, ctx.info()["ntt_fp64_mask"])
+    mask = ctx.info()["ntt_fp64_mask"]
+    peak = measured_peak_bfly_per_s(ctx.moduli, ps.limbs, mask)
+    peak_model = model_peak_bfly_per_s(ps.limbs, mask)
     line = {
         "metric": METRIC,
         "value": value,
@@ -584,7 +680,12 @@ def main():
                    "tuning_from_cache": bool(tune and tune["from_cache"])},
         "roofline": {"bound": "alu", "achieved": achieved / 1e9, "peak": peak / 1e9,
                      "unit": "Gbutterfly/s", "frac": achieved / peak,
-                     "ntt_fp64_limbs": [l for l in range(ps.limbs) if (ctx.info()["ntt_fp64_mask"] >> l) & 1],
+                     "peak_source": "measured: zinc_butterfly_rate, the kernels' butterflies in registers, "
+                                    "harmonic mean over the data limbs' arithmetic",
+                     "peak_rates_gbutterfly_per_s": {("fp64" if a else "integer"): v[0] / 1e9
+                                                     for a, v in sorted(_RATES.items())},
+                     "peak_model": peak_model / 1e9, "frac_model": achieved / peak_model,
+                     "ntt_fp64_limbs": [l for l in range(ps.limbs) if (mask >> l) & 1],
                      "traffic": traffic_from_profile(ws.name, main_name),
                      "kernel": ("k_encrypt" if ctx.get_tuning()["tile"][sch] == 16
                                 and not (ctx.get_tuning()["reg_epilogue"] >> sch) & 1 else "k_encrypt_tile")
@@ -604,6 +705,8 @@ def main():
         # the prime with rounding), the form of the paper's CPU baseline
         line["zinc_over_vanilla_sp"] = res["vanilla_sp"]["ms_per_step"] / res["zinc"]["ms_per_step"]
     line["encrypt_only"] = bench_encrypt_only(ctx, z, ids, ct, args.steps, args.warmup)
+    if not args.no_configs:
+        line["configs"] = bench_configs(args.steps, args.warmup, args.tune_cache)
     line["elementwise"] = bench_elementwise(ctx, ps, ws.batch, args.steps, args.warmup)
     if not args.no_mixed:
         del ct, z

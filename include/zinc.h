@@ -507,6 +507,18 @@ zinc_status zinc_ntt_inverse(zinc_ctx* ctx, uint32_t limb, uint64_t* d_poly, uin
 zinc_status zinc_sample(zinc_ctx* ctx, int kind, uint32_t tag, uint32_t limb,
                         const uint64_t* d_ct_ids, uint32_t batch, void* d_out, void* stream);
 
+/* Measurement aid: the device's peak rate of the forward transform's
+ * butterfly, the roofline denominator of the fused encryption kernels (an
+ * encryption's cost is its transforms, Theoretical Analysis section).  A
+ * full-occupancy grid keeps 16 residues per thread in registers and runs
+ * rounds of four radix-2 stages with the library's own butterfly: arith 0 =
+ * 64-bit Shoup with the lazy reduction every fourth stage (moduli in
+ * [2^20, 2^60)), arith 1 = exact FP64 (moduli in [2^20, 2^50)); twiddles are
+ * wave-uniform, nothing touches memory until a final checksum.  Synchronous:
+ * 200 ms of untimed launches, then `reps` (1..1000) launches timed with HIP
+ * events; *bfly_per_s = butterflies per second of the median launch. */
+zinc_status zinc_butterfly_rate(int arith, uint64_t q, uint32_t reps, double* bfly_per_s);
+
 /* Copy the device-resident keys and cache (device-to-device, on `stream`):
  * secret key s_hat [M][N], public key [2][M][N], cached Enc(0) [2][L][N]. */
 zinc_status zinc_export_keys(zinc_ctx* ctx, uint64_t* d_sk, uint64_t* d_pk, uint64_t* d_zero,

@@ -137,6 +137,7 @@ _SIGS = {
     "zinc_ntt_inverse": (ctypes.c_int, [_vp, _u32, _vp, _u32, _vp]),
     "zinc_sample": (ctypes.c_int, [_vp, ctypes.c_int, _u32, _u32, _vp, _u32, _vp, _vp]),
     "zinc_export_keys": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "zinc_butterfly_rate": (ctypes.c_int, [ctypes.c_int, ctypes.c_uint64, _u32, ctypes.POINTER(ctypes.c_double)]),
 }
 EXPORTED = tuple(_SIGS)
 
@@ -585,6 +586,14 @@ def serve_trace(ctxs, scheme: int, requests, arrival_ns, slots, ct=None, n_strea
     _check(lib.zinc_serve_trace(arr, len(ctxs), ctypes.byref(cfg), req.ctypes.data, arr_ns.ctypes.data,
                                 len(req), times.ctypes.data))
     return times
+
+
+def butterfly_rate(arith: int, q: int, reps: int = 9) -> float:
+    """Peak forward-transform butterflies per second of this GPU (arith 0:
+    integer Shoup, 1: exact FP64) for modulus q (zinc_butterfly_rate)."""
+    r = ctypes.c_double()
+    _check(load_library().zinc_butterfly_rate(int(arith), int(q), int(reps), ctypes.byref(r)))
+    return r.value
 
 
 def context_for(ps) -> Context:

@@ -13,7 +13,7 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libzinc.so")
 SOURCES = ["capi.cpp", "host_math.cpp", "plan.cpp", "server.cpp", "tune.cpp", "kernels.hip", "kernels_split.hip",
            "kernels_plan_zinc.hip", "kernels_plan_vanilla.hip", "kernels_tiles_zinc.hip", "kernels_tiles_vanilla.hip",
-           "kernels_elementwise.hip", "kernels_sp.hip", "kernels_sp_split.hip", "kernels_bfv.hip", "kernels_batch.hip"]
+           "kernels_elementwise.hip", "kernels_sp.hip", "kernels_sp_split.hip", "kernels_bfv.hip", "kernels_batch.hip", "kernels_rate.hip"]
 ARCH = os.environ.get("ZINC_OFFLOAD_ARCH", "gfx950")
 
 # Packed-FP32 instructions are disabled for all device code.

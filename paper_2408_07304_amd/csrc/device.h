@@ -252,6 +252,23 @@ __device__ __forceinline__ uint32_t tw_index(uint32_t tp, int c, int b, uint32_t
     return (smul << s) + ((tp | G::cpart(P, c)) >> (LO + b + 1));
 }
 
+// An exchange between the layouts of passes P1 and P2 stays inside each
+// wavefront when the wave-number bits of the thread id (those above its 64
+// lanes) sit on the same index bits in both layouts: every wave then owns the
+// same indices, hence the same LDS words, before and after.  The LDS executes
+// a wave's instructions in order, so such an exchange needs no workgroup
+// barrier, only a compiler barrier that keeps the wave's reads after its
+// writes.
+template <class G>
+__host__ __device__ constexpr bool wave_local(int p1, int p2) {
+    for (int b = 6; b < G::LOGT; ++b)
+        if (G::spread(p1, 1u << b) != G::spread(p2, 1u << b)) return false;
+    return true;
+}
+
+// Compiler barrier for LDS accesses exchanged within one wavefront.
+__device__ __forceinline__ void wave_lds_fence() { asm volatile("" ::: "memory"); }
+
 template <class G, int P, class T>
 __device__ __forceinline__ void lds_put(T* lds, const T (&v)[G::R], uint32_t t) {
     T* base = lds + pad(G::tpart(P, t));
@@ -265,6 +282,25 @@ __device__ __forceinline__ void lds_get(const T* lds, T (&v)[G::R], uint32_t t) 
 #pragma unroll
     for (int c = 0; c < G::R; ++c) v[c] = base[pad(G::cpart(P, c))];
 }
+
+// v from the layout of pass P1 to that of pass P2 through LDS: within each
+// wavefront when the layouts allow it (wave_local), else with workgroup
+// barriers before the writes (earlier readers of the words are done) and
+// after them.
+template <class G, int P1, int P2, class T>
+__device__ __forceinline__ void exchange(T* lds, T (&v)[G::R], uint32_t t) {
+    if constexpr (wave_local<G>(P1, P2)) {
+        wave_lds_fence();
+        lds_put<G, P1>(lds, v, t);
+        wave_lds_fence();
+    } else {
+        __syncthreads();
+        lds_put<G, P1>(lds, v, t);
+        __syncthreads();
+    }
+    lds_get<G, P2>(lds, v, t);
+}
+
 
 // A twiddle and its companion (Shoup factor, or w/q) are adjacent in the
 // tables at an even index: one 16-byte load.
@@ -338,10 +374,7 @@ template <class G, int P>
 __device__ __forceinline__ void fwd_rest(u64 (&v)[G::R], u64* lds, const u64* __restrict__ tw, uint32_t toff,
                                          uint32_t smul, u64 q, u64 q2, uint32_t t) {
     if constexpr (P < G::NPASS) {
-        __syncthreads();
-        lds_put<G, P - 1>(lds, v, t);
-        __syncthreads();
-        lds_get<G, P>(lds, v, t);
+        exchange<G, P - 1, P>(lds, v, t);
         fwd_pass<G, P>(v, t, tw, toff, smul, q, q2);
         fwd_rest<G, P + 1>(v, lds, tw, toff, smul, q, q2, t);
     }
@@ -365,10 +398,7 @@ template <class G, int P>
 __device__ __forceinline__ void inv_rest(u64 (&v)[G::R], u64* lds, const u64* __restrict__ itw, uint32_t toff,
                                          uint32_t smul, u64 q, u64 q2, uint32_t t) {
     if constexpr (P >= 0) {
-        __syncthreads();
-        lds_put<G, P + 1>(lds, v, t);
-        __syncthreads();
-        lds_get<G, P>(lds, v, t);
+        exchange<G, P + 1, P>(lds, v, t);
         inv_pass<G, P>(v, t, itw, toff, smul, q, q2);
         inv_rest<G, P - 1>(v, lds, itw, toff, smul, q, q2, t);
     }
@@ -387,7 +417,8 @@ __device__ __forceinline__ void ntt_inv(u64 (&v)[G::R], u64* lds, const u64* __r
     inv_rest<G, PL - 1>(v, lds, itw, toff, smul, q, q2, t);
 }
 
-// Write v (last forward pass layout) to LDS so that lds[pad(i)] is coefficient i.
+// Write v (last forward pass layout) to LDS so that lds[pad(i)] is coefficient i
+// (across waves: workgroup barriers).
 template <class G, class T>
 __device__ __forceinline__ void to_natural(T* lds, const T (&v)[G::R], uint32_t t_) {
     const uint32_t t = opaque_tid(t_);
@@ -472,10 +503,7 @@ __device__ __forceinline__ void fwd_rest_fp(double (&v)[G::R], double* lds, cons
                                             uint32_t toff, uint32_t smul, double q, double qinv, bool reduce,
                                             uint32_t t) {
     if constexpr (P < G::NPASS) {
-        __syncthreads();
-        lds_put<G, P - 1>(lds, v, t);
-        __syncthreads();
-        lds_get<G, P>(lds, v, t);
+        exchange<G, P - 1, P>(lds, v, t);
         fwd_pass_fp<G, P>(v, t, tw, toff, smul, q, qinv, reduce);
         fwd_rest_fp<G, P + 1>(v, lds, tw, toff, smul, q, qinv, reduce, t);
     }

@@ -58,22 +58,30 @@ struct LimbNtt {
 
     // Transform the pass-0 inputs given by in(c) (integer path: a residue in
     // [0, 2q); FP path: an exact integer of magnitude at most q, as double).
-    template <class InInt, class InFp>
-    __device__ __forceinline__ void run(InInt in_int, InFp in_fp) const {
+    // hook() runs after the last pass, before the exchange into natural
+    // order (early loads of epilogue operands go there).
+    template <class InInt, class InFp, class Hook>
+    __device__ __forceinline__ void run(InInt in_int, InFp in_fp, Hook hook) const {
         if (fp()) {
             double v[G::R];
 #pragma unroll
             for (int c = 0; c < G::R; ++c) v[c] = in_fp(c);
             double* ld = reinterpret_cast<double*>(lds);
             ntt_fwd_fp<G>(v, ld, tw_fp, limb, qd, qinv, mode == 2, t);
+            hook();
             to_natural<G>(ld, v, t);
         } else {
             u64 v[G::R];
 #pragma unroll
             for (int c = 0; c < G::R; ++c) v[c] = in_int(c);
             ntt_fwd<G>(v, lds, tw, limb, q, q2, t);
+            hook();
             to_natural<G>(lds, v, t);
         }
+    }
+    template <class InInt, class InFp>
+    __device__ __forceinline__ void run(InInt in_int, InFp in_fp) const {
+        run(in_int, in_fp, []() {});
     }
 
     // The same transform, leaving canonical residues in registers: res[c] is
@@ -136,29 +144,47 @@ __device__ __forceinline__ void store_pair_final(u64* p, u64 a, u64 b) {
 }
 
 // Transform one polynomial of a limb and hand every coefficient pair the
-// thread owns to epi(k, v_k, v_k+1) (k even, canonical values).  REG = false:
-// back to natural order through LDS, so a wave's accesses are contiguous;
-// REG = true: straight from the registers of the last pass, whose runs of
-// consecutive coefficients give 2^K-strided accesses but no LDS round trip.
-// Which is faster depends on the ring degree and the scheme (autotuned).
-template <bool REG, class G, class InInt, class InFp, class Epi>
-__device__ __forceinline__ void transform_store(const LimbNtt<G>& nt, uint32_t t, InInt in_int, InFp in_fp,
-                                                Epi epi) {
+// thread owns to epi(k, v_k, v_k+1, pre(k)) (k even, canonical values; pre(k)
+// an operand of the epilogue loaded for that pair).  REG = false: back to
+// natural order through LDS, so that each store instruction of a workgroup's
+// waves covers one contiguous span; pre(k) is issued after the last pass, so
+// its latency overlaps that exchange.  REG = true: straight from the
+// registers of the last pass, whose runs of consecutive coefficients give
+// 2^K-strided accesses but no LDS round trip.  Which is faster depends on the
+// ring degree and the scheme (autotuned).
+template <bool REG, class G, class InInt, class InFp, class Pre, class Epi>
+__device__ __forceinline__ void transform_store_pre(const LimbNtt<G>& nt, uint32_t t, InInt in_int, InFp in_fp,
+                                                    Pre pre, Epi epi) {
     if constexpr (REG) {
         u64 r[G::R];
         nt.run_regs(in_int, in_fp, r);
         const uint32_t tt = opaque_tid(t);
 #pragma unroll
-        for (int c = 0; c < G::R; c += 2) epi(out_index<G>(tt, c), r[c], r[c + 1]);
+        for (int c = 0; c < G::R; c += 2) {
+            const uint32_t k = out_index<G>(tt, c);
+            epi(k, r[c], r[c + 1], pre(k));
+        }
     } else {
-        nt.run(in_int, in_fp);
+        decltype(pre(0u)) pv[G::R / 2];
+        nt.run(in_int, in_fp, [&]() {
+            const uint32_t tt = opaque_tid(t);
+#pragma unroll
+            for (int i = 0; i < G::R / 2; ++i) pv[i] = pre(2 * (tt + G::T * i));
+        });
         const uint32_t tt = opaque_tid(t);
 #pragma unroll
         for (int i = 0; i < G::R / 2; ++i) {
             const uint32_t k = 2 * (tt + G::T * i);
-            epi(k, nt.canon(k), nt.canon(k + 1));
+            epi(k, nt.canon(k), nt.canon(k + 1), pv[i]);
         }
     }
+}
+
+template <bool REG, class G, class InInt, class InFp, class Epi>
+__device__ __forceinline__ void transform_store(const LimbNtt<G>& nt, uint32_t t, InInt in_int, InFp in_fp,
+                                                Epi epi) {
+    transform_store_pre<REG>(nt, t, in_int, in_fp, [](uint32_t) { return 0; },
+                             [&](uint32_t k, u64 a, u64 b, int) { epi(k, a, b); });
 }
 
 // A Gaussian error coefficient x as the scheme adds it, for the integer and the
@@ -261,21 +287,21 @@ __device__ __forceinline__ void encrypt_item_g(const DevParams& p, const double*
             // c1 = zero1 + NTT(m + e1')
             const u64* z1 = p.zero + (size_t)l * N;
             u64* c1 = ct + (size_t)l * N;
-            transform_store<REG_EPI>(nt, t, [&](int c) { return msg.ri(c); }, [&](int c) { return msg.rf(c); },
-                                     [&](uint32_t k, u64 a, u64 b) {
-                                         const u64x2 z = load_pair(z1 + k);
-                                         final_store(c1 + k, addmod(a, z.x, lc.q), addmod(b, z.y, lc.q));
-                                     });
+            transform_store_pre<REG_EPI>(nt, t, [&](int c) { return msg.ri(c); }, [&](int c) { return msg.rf(c); },
+                                         [&](uint32_t k) { return load_pair(z1 + k); },
+                                         [&](uint32_t k, u64 a, u64 b, u64x2 z) {
+                                             final_store(c1 + k, addmod(a, z.x, lc.q), addmod(b, z.y, lc.q));
+                                         });
             // c2 = zero2 + NTT(e2')
             const Packed8<R> e2l = e2.fresh();
             const u64* z2 = p.zero + (size_t)(L + l) * N;
             u64* c2 = ct + (size_t)(L + l) * N;
-            transform_store<REG_EPI>(nt, t, [&](int c) { return noise_ri<BGV>(e2l.get(c), p.noise_t, lc); },
-                                     [&](int c) { return noise_rf<BGV>(e2l.get(c), p.noise_t, lc); },
-                                     [&](uint32_t k, u64 a, u64 b) {
-                                         const u64x2 z = load_pair(z2 + k);
-                                         final_store(c2 + k, addmod(a, z.x, lc.q), addmod(b, z.y, lc.q));
-                                     });
+            transform_store_pre<REG_EPI>(nt, t, [&](int c) { return noise_ri<BGV>(e2l.get(c), p.noise_t, lc); },
+                                         [&](int c) { return noise_rf<BGV>(e2l.get(c), p.noise_t, lc); },
+                                         [&](uint32_t k) { return load_pair(z2 + k); },
+                                         [&](uint32_t k, u64 a, u64 b, u64x2 z) {
+                                             final_store(c2 + k, addmod(a, z.x, lc.q), addmod(b, z.y, lc.q));
+                                         });
         }
     } else {
         Packed8<R> u, e1, e2;

@@ -146,13 +146,13 @@ void gaussian_cdt(double sigma, uint64_t out[kCdtLen]) {
 // whole table).
 void gaussian_buckets(const uint64_t cdt[kCdtLen], uint64_t out[kCdtBuckets]) {
     for (int b = 0; b < kCdtBuckets; ++b) {
-        const uint64_t start = (uint64_t)b << 56;
+        const uint64_t start = (uint64_t)b << kCdtShift;
         uint64_t lo = 0, inner = 0, thr = 0;
         for (int i = 0; i < kCdtLen; ++i) {
             if (cdt[i] <= start) ++lo;
-            else if ((cdt[i] >> 56) == (uint64_t)b) { ++inner; thr = cdt[i]; }
+            else if ((cdt[i] >> kCdtShift) == (uint64_t)b) { ++inner; thr = cdt[i]; }
         }
-        if (inner == 1) out[b] = (lo << 56) | (thr & ((1ull << 56) - 1));
+        if (inner == 1) out[b] = (lo << 56) | (thr & kCdtLowMask);
         else if (inner == 0 && lo > 0) out[b] = (lo - 1) << 56;
         else out[b] = 1ull << 63;
     }

@@ -14,7 +14,10 @@ namespace zinc {
 
 constexpr int kCdtLen = 38;       // support [-19, 19] -> 38 thresholds
 constexpr int kCdtPad = 64;       // padded to a power of two for the device search
-constexpr int kCdtBuckets = 256;  // first-level table over the top 8 bits of the uniform
+constexpr int kCdtBucketBits = 10;                // first-level table over the top 10 bits of the uniform
+constexpr int kCdtBuckets = 1 << kCdtBucketBits;
+constexpr int kCdtShift = 64 - kCdtBucketBits;   // bucket = u >> kCdtShift
+constexpr uint64_t kCdtLowMask = (1ull << kCdtShift) - 1;
 constexpr int kCdtTab = kCdtPad + kCdtBuckets;   // words of the device table
 constexpr int kTail = 19;
 

@@ -99,25 +99,25 @@ static int test_gaussian_buckets() {
     for (int i = 0; i < 200000; ++i) us.push_back(rng());
     for (int i = 0; i < zinc::kCdtLen; ++i)
         for (int d = -1; d <= 1; ++d) us.push_back(cdt[i] + (uint64_t)(int64_t)d);
-    for (uint64_t b = 0; b < 256; ++b) {
-        us.push_back(b << 56);
-        us.push_back(((b + 1) << 56) - 1);
+    for (uint64_t b = 0; b < (uint64_t)zinc::kCdtBuckets; ++b) {
+        us.push_back(b << zinc::kCdtShift);
+        us.push_back(((b + 1) << zinc::kCdtShift) - 1);
     }
     int fallback = 0;
     for (uint64_t u : us) {
         int count = 0;
         for (int i = 0; i < zinc::kCdtLen; ++i) count += u >= cdt[i];
-        const uint64_t e = bucket[u >> 56];
+        const uint64_t e = bucket[u >> zinc::kCdtShift];
         if (e >> 63) {
             ++fallback;
             continue;
         }
-        const uint64_t thr = (u & 0xFF00000000000000ull) | (e & 0x00FFFFFFFFFFFFFFull);
+        const uint64_t thr = (u & ~zinc::kCdtLowMask) | (e & zinc::kCdtLowMask);
         CHECK((int)((e >> 56) & 63) + (u >= thr ? 1 : 0) == count);
     }
     int flagged = 0;
-    for (int b = 0; b < 256; ++b) flagged += (int)(bucket[b] >> 63);
-    CHECK(flagged == 2 && (bucket[0] >> 63) && (bucket[255] >> 63));
+    for (int b = 0; b < zinc::kCdtBuckets; ++b) flagged += (int)(bucket[b] >> 63);
+    CHECK(flagged == 2 && (bucket[0] >> 63) && (bucket[zinc::kCdtBuckets - 1] >> 63));
     CHECK(fallback > 0);
     return 0;
 }

@@ -437,11 +437,16 @@ __device__ __forceinline__ void to_natural(T* lds, const T (&v)[G::R], uint32_t 
 // rounded quotient wq = fl(w/q), for |y| < 2^53:
 //   k = rint(y * wq), h = fl(y w), l = fma(y, w, -h) = y w - h exactly,
 //   r = fma(-k, q, h) = h - k q exactly (|h - k q| < 2^53), t = r + l exactly,
-// so t = y w - k q with |t| <= q (1/2 + |y| 2^-52).  Values are not reduced
-// between stages: from |x| <= q they stay below 20 q over 15 stages, which is
-// below 2^52 for q < 2^47.  Moduli in [2^47, 2^50) are rounded into
-// [-q/2, q/2] at the start of every pass (at most five stages), which keeps
-// them below 2^52 as well.
+// so t = y w - k q with |t| <= q (1/2 + |y| 2^-52), and x +- t is exact while
+// it stays below 2^53.  A stage therefore raises a bound B on |x|, |y| to
+// B + q (1/2 + B 2^-52).  Moduli below 2^47 are not reduced inside the
+// transform: from inputs up to 2q + 64 (a residue, the cached Enc(0)'s
+// coefficient and an error) every value stays below 2^52 over 15 stages.
+// Moduli in [2^47, 2^50) are rounded into [-q/2 - 1, q/2 + 1] at the start
+// of every pass but the first; with first-pass inputs up to q + 64 the
+// values stay below 2^53 (the worst case, a five-stage first pass near
+// q = 2^50, reaches about 2^52.4).  A CPU test propagates these bounds for
+// every thread geometry.
 
 #pragma clang fp contract(off)
 __device__ __forceinline__ double fp_mulmod(double y, double w, double wq, double q) {

@@ -3,8 +3,9 @@
 // encrypts it.  A unit is 4, 2, 1 or 1 ciphertexts of one context of ring
 // degree 4096, 8192, 16384 or 32768: the 1024 threads split into that many
 // groups of N/16 threads which run the same code in lockstep (their barriers
-// coincide), each group with its own slice of the 136 KiB LDS buffer.  Units
-// are ordered by decreasing cost, so the largest ones start first.
+// coincide), each group with its own slice of the 136 KiB LDS buffer.  A
+// ring-degree-32768 unit may cover a group of the ciphertext's limbs only.
+// Units are ordered by decreasing cost, so the largest ones start first.
 #pragma once
 #include "split_common.h"
 
@@ -36,10 +37,9 @@ k_plan(const DevParams* __restrict__ ctxs, const PlanItem* __restrict__ items, c
     __shared__ u64 lds[kPlanLds];
     __shared__ u64 tab[kCdtTab];
     __shared__ uint32_t s_unit;
-    const uint32_t t = threadIdx.x;
     for (;;) {
         __syncthreads();
-        if (t == 0) s_unit = atomicAdd(counter, 1u);
+        if (threadIdx.x == 0) s_unit = atomicAdd(counter, 1u);
         __syncthreads();
         // the same value in every lane: taken from the first lane so that the
         // unit and its context are read with scalar loads into scalar registers
@@ -47,6 +47,11 @@ k_plan(const DevParams* __restrict__ ctxs, const PlanItem* __restrict__ items, c
         if (ui >= n_units) break;                     // every wave of the workgroup leaves here
         const PlanUnit un = units[ui];
         const DevParams& p = ctxs[un.ctx];   // fields read on demand (scalar loads)
+        // The thread index as a value the compiler cannot see through, taken
+        // afresh in every iteration: otherwise every address derived from it
+        // alone is hoisted out of the work loop and held in registers across
+        // all four ring degrees' code (hundreds of spilled registers).
+        const uint32_t t = opaque_tid(threadIdx.x);
         load_cdt(tab, p.cdt, t);
         switch (un.log_n) {
             case 12: run_group<12, SCHEME>(p, items, un, slots, ct, dummy, lds, tab, t); break;
@@ -56,7 +61,7 @@ k_plan(const DevParams* __restrict__ ctxs, const PlanItem* __restrict__ items, c
                 const PlanItem it = items[un.first];
                 u64* out = (it.dummy ? dummy : ct) + it.ct_off;
                 encrypt_item_split<SCHEME, true>(p, slots + it.slot_off, 32768 / 2, nullptr, it.ct_id, out, lds,
-                                                 tab, t);
+                                                 tab, t, un.l0, un.l1);
             }
         }
     }

@@ -45,26 +45,41 @@ int device_cu_count() {
     return cus > 0 ? cus : 256;
 }
 
+double plan_unit_cost(const zinc_ctx& c, const PlanUnit& u) {
+    return (double)u.count * c.n * c.log_n * ((double)(u.l1 - u.l0) + 1.0);
+}
+
 uint64_t build_plan_tables(zinc_ctx* const* ctxs, uint32_t n_ctx, const zinc_item* items, uint32_t n_items,
-                           std::vector<PlanItem>& dev_items, std::vector<PlanUnit>& units) {
-    // Contexts in decreasing cost per ciphertext, so the largest units come
-    // first (longest-processing-time order).
-    std::vector<uint32_t> order(n_ctx);
-    for (uint32_t c = 0; c < n_ctx; ++c) order[c] = c;
-    auto cost = [&](uint32_t c) { return (double)ctxs[c]->L * ctxs[c]->n * ctxs[c]->log_n; };
-    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return cost(a) > cost(b); });
+                           std::vector<PlanItem>& dev_items, std::vector<PlanUnit>& units, uint32_t round) {
     dev_items.clear();
     units.clear();
     uint64_t dummy_words = 0;
     std::vector<std::vector<uint32_t>> per_ctx(n_ctx);
     for (uint32_t i = 0; i < n_items; ++i) per_ctx[items[i].ctx_idx].push_back(i);
-    for (uint32_t c : order) {
+    // Ring degree 32768 (one ciphertext per unit): the ciphertexts beyond the
+    // last whole round of `round` units would run in a partial round of their
+    // own while the other workgroups idle; split into limb groups, they spread
+    // over all workgroups (each group redraws the same noise and re-encodes
+    // the message, about one limb's work).
+    uint32_t n32 = 0;
+    for (uint32_t c = 0; c < n_ctx; ++c)
+        if (ctxs[c]->log_n == 15) n32 += (uint32_t)per_ctx[c].size();
+    const uint32_t tail = round ? n32 % round : 0;
+    uint32_t seen32 = 0;
+    for (uint32_t c = 0; c < n_ctx; ++c) {
         const zinc_ctx* cx = ctxs[c];
         const uint32_t g = plan_units_per_group(cx->log_n);
         const uint64_t ct_words = 2ull * cx->L * cx->n;
         const auto& lst = per_ctx[c];
         for (size_t s = 0; s < lst.size(); s += g) {
-            units.push_back(PlanUnit{c, cx->log_n, (uint32_t)dev_items.size(), g});
+            if (cx->log_n == 15 && seen32++ >= n32 - tail) {
+                const uint32_t parts = std::min(kPlanSplit, cx->L);
+                for (uint32_t j = 0; j < parts; ++j)
+                    units.push_back(PlanUnit{c, cx->log_n, (uint32_t)dev_items.size(), 1u, j * cx->L / parts,
+                                             (j + 1) * cx->L / parts});
+            } else {
+                units.push_back(PlanUnit{c, cx->log_n, (uint32_t)dev_items.size(), g, 0u, cx->L});
+            }
             for (uint32_t k = 0; k < g; ++k) {
                 if (s + k < lst.size()) {
                     const zinc_item& it = items[lst[s + k]];
@@ -77,6 +92,10 @@ uint64_t build_plan_tables(zinc_ctx* const* ctxs, uint32_t n_ctx, const zinc_ite
             }
         }
     }
+    // longest-processing-time order: the largest units start first
+    std::stable_sort(units.begin(), units.end(), [&](const PlanUnit& a, const PlanUnit& b) {
+        return plan_unit_cost(*ctxs[a.ctx], a) > plan_unit_cost(*ctxs[b.ctx], b);
+    });
     return dummy_words;
 }
 
@@ -119,7 +138,8 @@ zinc_status zinc_plan_create(zinc_ctx* const* ctxs, uint32_t n_ctx, const zinc_i
     }
     std::vector<PlanItem> dev_items;
     std::vector<PlanUnit> units;
-    const uint64_t dummy_words = build_plan_tables(ctxs, n_ctx, items, n_items, dev_items, units);
+    const int cus = device_cu_count();
+    const uint64_t dummy_words = build_plan_tables(ctxs, n_ctx, items, n_items, dev_items, units, (uint32_t)cus);
     zinc_plan* p = new (std::nothrow) zinc_plan();
     if (!p) return plan_fail(ZINC_E_NOMEM, "host allocation failed");
     p->ctxs.assign(ctxs, ctxs + n_ctx);
@@ -149,7 +169,6 @@ zinc_status zinc_plan_create(zinc_ctx* const* ctxs, uint32_t n_ctx, const zinc_i
         delete p;
         return plan_fail(ZINC_E_HIP, std::string("zinc_plan_create: upload failed: ") + hipGetErrorString(e));
     }
-    const int cus = device_cu_count();
     PlanDev& d = p->dev;
     d.ctxs = reinterpret_cast<const DevParams*>(base);
     d.items = reinterpret_cast<const PlanItem*>(base + b_ctx);

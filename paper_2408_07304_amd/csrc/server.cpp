@@ -167,7 +167,7 @@ zinc_status launch(zinc_server* s, uint32_t lane_idx) {
     }
     if (l.tickets.empty()) return ZINC_OK;
     (void)build_plan_tables(s->ctxs.data(), (uint32_t)s->ctxs.size(), s->items.data(), (uint32_t)s->items.size(),
-                            s->dev_items, s->units);
+                            s->dev_items, s->units, (uint32_t)s->cus);
     if (s->dev_items.size() > s->item_cap || s->units.size() > s->unit_cap)
         return plan_fail(ZINC_E_INVAL, "zinc_server_progress: batch tables exceed their capacity");
     std::memcpy(l.h_items, s->dev_items.data(), sizeof(PlanItem) * s->dev_items.size());
@@ -243,9 +243,9 @@ zinc_status zinc_server_create(zinc_ctx* const* ctxs, uint32_t n_ctx, const zinc
     s->arena = Arena(budget);
     s->cus = device_cu_count();
     // Per-batch table capacity: every plaintext plus the padding of one
-    // partial unit per context.
+    // partial unit per context; a plaintext is at most kPlanSplit units.
     s->item_cap = cfg->max_batch + 3ull * n_ctx;
-    s->unit_cap = cfg->max_batch + (size_t)n_ctx;
+    s->unit_cap = (size_t)kPlanSplit * cfg->max_batch + (size_t)n_ctx;
     const uint64_t dummy_words = std::max<uint64_t>(1, plan_dummy_words(ctxs, n_ctx));
     auto al = [](size_t x) { return (x + kAlign - 1) & ~size_t(kAlign - 1); };
     const size_t b_ctx = al(sizeof(DevParams) * n_ctx), b_items = al(sizeof(PlanItem) * s->item_cap);

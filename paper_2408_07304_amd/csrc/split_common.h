@@ -247,15 +247,19 @@ __device__ __forceinline__ void intt_split(const DevParams& p, const LimbConst& 
 // Encrypt one ciphertext of ring degree 32768 with all TS threads of the
 // workgroup; lds holds LdsWords<NH> words, tab the chi table.  BGV = true
 // (integer plaintexts only): every Gaussian error is scaled by the plaintext
-// modulus p.noise_t (Eq. 13); the ternary u is not.
+// modulus p.noise_t (Eq. 13); the ternary u is not.  Only data limbs
+// [l0, min(l1, L)) are computed (the noise and the message are the
+// ciphertext's own whatever the range, so separate ranges of one ciphertext
+// may run in separate workgroups); the stash is the c1 slot of the range's
+// last limb.
 template <int SCHEME, bool FROM_SLOTS, bool BGV = false>
 __device__ __forceinline__ void encrypt_item_split(const DevParams& p, const double* slots, uint32_t n_slots,
                                                    const u64* pt, u64 ct_id, u64* ct, u64* lds, const u64* tab,
-                                                   uint32_t t) {
+                                                   uint32_t t, uint32_t l0 = 0, uint32_t l1 = ~0u) {
     using namespace split;
     static_assert(!(FROM_SLOTS && BGV), "BGV encrypts integer plaintexts");
-    const uint32_t L = p.L;
-    long long* stash = reinterpret_cast<long long*>(ct + (size_t)(L - 1) * NF);
+    const uint32_t L = p.L, le = l1 < L ? l1 : L;
+    long long* stash = reinterpret_cast<long long*>(ct + (size_t)(le - 1) * NF);
 
     if constexpr (FROM_SLOTS) {
         long long mlo[RS], mhi[RS];
@@ -334,7 +338,7 @@ __device__ __forceinline__ void encrypt_item_split(const DevParams& p, const dou
         sample_gauss_split(e1, p, tab, ct_id, TAG_E1Z, t);
         sample_gauss_split(e2, p, tab, ct_id, TAG_E2Z, t);
 #pragma unroll 1
-        for (uint32_t l = 0; l < L; ++l) {
+        for (uint32_t l = l0; l < le; ++l) {
             const LimbConst lc = p.limbs[l];
             const SplitLimb sl(p, lc, l, lds, t);
             u64* c1 = ct + (size_t)l * NF;
@@ -358,7 +362,7 @@ __device__ __forceinline__ void encrypt_item_split(const DevParams& p, const dou
         sample_gauss_split(e2, p, tab, ct_id, TAG_E2, t);
         const uint32_t M = p.M;
 #pragma unroll 1
-        for (uint32_t l = 0; l < L; ++l) {
+        for (uint32_t l = l0; l < le; ++l) {
             const LimbConst lc = p.limbs[l];
             const SplitLimb sl(p, lc, l, lds, t);
             u64* c1 = ct + (size_t)l * NF;

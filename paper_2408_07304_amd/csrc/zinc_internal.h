@@ -107,12 +107,15 @@ struct PlanItem {
 };
 
 // A unit of work: `count` consecutive items of one context, all encrypted by
-// one workgroup (4, 2, 1, 1 items for ring degree 4096, 8192, 16384, 32768).
+// one workgroup (4, 2, 1, 1 items for ring degree 4096, 8192, 16384, 32768),
+// over data limbs [l0, l1) (all of them, except for ring degree 32768, where
+// the ciphertexts of a last partial round of units are split into limb groups).
 struct PlanUnit {
     uint32_t ctx;
     uint32_t log_n;
     uint32_t first;
     uint32_t count;
+    uint32_t l0, l1;
 };
 
 struct PlanDev {
@@ -228,12 +231,20 @@ hipError_t launch_plan(const PlanDev& d, int scheme, const double* slots, uint64
 
 // plan tables (plan.cpp), shared by plans and the server
 uint32_t plan_units_per_group(uint32_t log_n);
-// Group items by context, contexts in decreasing cost per ciphertext, and cut
-// each group into units of plan_units_per_group items; a partial unit is
-// padded with copies of its first item whose outputs go to a dummy buffer.
-// Returns the dummy buffer's size in words (at most plan_dummy_words).
+// Group items by context and cut each group into units of
+// plan_units_per_group items; a partial unit is padded with copies of its
+// first item whose outputs go to a dummy buffer.  Ciphertexts of ring degree
+// 32768 that would form a last partial round of `round` units (one per
+// workgroup of the persistent launch) are split into up to four limb groups.
+// Units are ordered by decreasing estimated cost (plan_unit_cost), so the
+// largest start first.  Returns the dummy buffer's size in words (at most
+// plan_dummy_words).
 uint64_t build_plan_tables(zinc_ctx* const* ctxs, uint32_t n_ctx, const zinc_item* items, uint32_t n_items,
-                           std::vector<PlanItem>& dev_items, std::vector<PlanUnit>& units);
+                           std::vector<PlanItem>& dev_items, std::vector<PlanUnit>& units, uint32_t round);
+// Estimated cost of a unit (relative): per item, N log N times the unit's
+// limbs plus one limb's worth for the encoding and sampling every unit does.
+double plan_unit_cost(const zinc_ctx& c, const PlanUnit& u);
+constexpr uint32_t kPlanSplit = 4;        // limb groups of a split ring-degree-32768 ciphertext
 uint64_t plan_dummy_words(zinc_ctx* const* ctxs, uint32_t n_ctx);
 int device_cu_count();
 zinc_status plan_fail(zinc_status code, const std::string& msg);

@@ -5,6 +5,7 @@
 #include <stdio.h>
 
 #include <algorithm>
+#include <map>
 #include <random>
 #include <set>
 #include <vector>
@@ -67,26 +68,44 @@ static int test_plan_tables() {
         items.push_back(zinc_item{(uint32_t)(rng() % 4), 0u, 1000ull * i, 7000ull * i, 5ull * i + 1});
     std::vector<zinc::PlanItem> di;
     std::vector<zinc::PlanUnit> un;
-    const uint64_t dummy = zinc::build_plan_tables(cp.data(), 4, items.data(), (uint32_t)items.size(), di, un);
+    const uint32_t round = 16;                           // workgroups of the persistent launch
+    const uint64_t dummy =
+        zinc::build_plan_tables(cp.data(), 4, items.data(), (uint32_t)items.size(), di, un, round);
     CHECK(dummy <= zinc::plan_dummy_words(cp.data(), 4));
-    std::multiset<uint64_t> seen;
+    std::map<uint64_t, uint32_t> limbs_done;             // ct_id -> limbs covered (each limb once)
     double last_cost = 1e300;
+    uint32_t n32 = 0, split_units = 0;
+    for (const zinc_item& it : items) n32 += ctx[it.ctx_idx].log_n == 15;
     for (const zinc::PlanUnit& u : un) {
         const zinc_ctx& c = ctx[u.ctx];
         CHECK(u.log_n == c.log_n && u.count == zinc::plan_units_per_group(c.log_n));
-        const double cost = (double)c.L * c.n * c.log_n;
+        CHECK(u.l0 < u.l1 && u.l1 <= c.L);
+        if (u.l1 - u.l0 < c.L) {
+            CHECK(c.log_n == 15);                        // only ring degree 32768 is split
+            ++split_units;
+        }
+        const double cost = zinc::plan_unit_cost(c, u);
         CHECK(cost <= last_cost);                        // longest units first
         last_cost = cost;
         for (uint32_t k = 0; k < u.count; ++k) {
             const zinc::PlanItem& it = di[u.first + k];
             CHECK(it.ctx == u.ctx);
-            if (it.dummy) CHECK(it.ct_off + 2ull * c.L * c.n <= dummy);
-            else seen.insert(it.ct_id);
+            if (it.dummy) {
+                CHECK(it.ct_off + 2ull * c.L * c.n <= dummy);
+            } else {
+                uint32_t& m = limbs_done[it.ct_id];
+                for (uint32_t l = u.l0; l < u.l1; ++l) {
+                    CHECK(!((m >> l) & 1u));
+                    m |= 1u << l;
+                }
+            }
         }
         CHECK(!di[u.first].dummy);                       // a unit starts with a real item
     }
-    CHECK(seen.size() == items.size());
-    for (const zinc_item& it : items) CHECK(seen.count(it.ct_id) == 1);
+    // the ciphertexts beyond the last whole round of 16 are split in four
+    CHECK(split_units == (n32 % round) * zinc::kPlanSplit);
+    CHECK(limbs_done.size() == items.size());
+    for (const zinc_item& it : items) CHECK(limbs_done[it.ct_id] == (1u << ctx[it.ctx_idx].L) - 1u);
     return 0;
 }
 

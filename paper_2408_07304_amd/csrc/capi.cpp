@@ -169,6 +169,7 @@ zinc_status zinc_ctx_create(const zinc_params* p, zinc_ctx** out) {
     const size_t o_pk = take(nb * 2 * M), o_pks = take(nb * 2 * M);
     const size_t o_zero = take(nb * 2 * L), o_pkp = take(nb * 2 * L), o_pkps = take(nb * 2 * L);
     const size_t o_err = take(256);
+    const size_t o_self = take(sizeof(DevParams));
     char* base = nullptr;
     hipError_t e = hipMalloc(&base, off);
     if (e != hipSuccess) {
@@ -220,6 +221,13 @@ zinc_status zinc_ctx_create(const zinc_params* p, zinc_ctx** out) {
     d.pkp = reinterpret_cast<const uint64_t*>(base + o_pkp);
     d.pkp_sh = reinterpret_cast<const uint64_t*>(base + o_pkps);
     d.err = reinterpret_cast<uint32_t*>(base + o_err);
+    d.self = reinterpret_cast<const DevParams*>(base + o_self);
+    e = hipMemcpy(base + o_self, &d, sizeof(DevParams), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(base);
+        delete c;
+        return hip_fail(e, "parameter upload");
+    }
     *out = c;
     return ZINC_OK;
 }
@@ -468,6 +476,9 @@ zinc_status zinc_set_bgv(zinc_ctx* c, uint64_t t) {
     c->dev.noise_t = t;
     c->keyed = false;
     c->precomputed = false;
+    const hipError_t e = hipMemcpy(const_cast<DevParams*>(c->dev.self), &c->dev, sizeof(DevParams),
+                                   hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "zinc_set_bgv: parameter upload");
     return ZINC_OK;
 }
 

@@ -15,7 +15,8 @@ namespace zinc {
 // ---------------------------------------------------------------------------
 template <int LOGN, int SCHEME, bool FROM_SLOTS, bool BGV = false>
 __global__ void __launch_bounds__(Cfg<LOGN>::G::T) __attribute__((amdgpu_waves_per_eu(4)))
-k_encrypt(DevParams p, EncArgs a) {
+k_encrypt(typename ParamArg<LOGN>::type pa, EncArgs a) {
+    const DevParams& p = deref(pa);
     using G = typename Cfg<LOGN>::G;
     constexpr int N = G::N;
     __shared__ u64 lds[LdsWords<N>::value];
@@ -278,7 +279,7 @@ hipError_t launch_encrypt_pt(const DevParams& p, int scheme, const uint64_t* pt,
     EncArgs a{nullptr, 0, (const u64*)pt, (const u64*)ct_ids, (u64*)ct, reserved_ok ? 1u : 0u};
     const bool bgv = p.noise_t > 1;
 #define G_(LN, SCH, B) \
-    hipLaunchKernelGGL((k_encrypt<LN, SCH, false, B>), dim3(batch), dim3(Cfg<LN>::G::T), 0, s, p, a)
+    hipLaunchKernelGGL((k_encrypt<LN, SCH, false, B>), dim3(batch), dim3(Cfg<LN>::G::T), 0, s, ParamArg<LN>::of(p), a)
 #define F(LN)                                        \
     if (scheme == ZINC_SCHEME_ZINC) {                \
         if (bgv) G_(LN, ZINC_SCHEME_ZINC, true);     \
@@ -301,10 +302,10 @@ hipError_t launch_encrypt_slots(const DevParams& p, int scheme, const double* sl
 #define F(LN)                                                                                         \
     if (scheme == ZINC_SCHEME_ZINC)                                                                   \
         hipLaunchKernelGGL((k_encrypt<LN, ZINC_SCHEME_ZINC, true>), dim3(batch), dim3(Cfg<LN>::G::T), \
-                           0, s, p, a);                                                               \
+                           0, s, ParamArg<LN>::of(p), a);                                                               \
     else                                                                                              \
         hipLaunchKernelGGL((k_encrypt<LN, ZINC_SCHEME_VANILLA, true>), dim3(batch),                  \
-                           dim3(Cfg<LN>::G::T), 0, s, p, a)
+                           dim3(Cfg<LN>::G::T), 0, s, ParamArg<LN>::of(p), a)
     ZINC_DISPATCH_LOGN(p.log_n, F)
 #undef F
     return hipGetLastError();

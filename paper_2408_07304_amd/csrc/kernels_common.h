@@ -15,6 +15,24 @@ struct Cfg<13> { using G = Geom<13, 9>; };
 template <>
 struct Cfg<14> { using G = Geom<14, 10>; };
 
+// How a kernel of ring degree 2^LOGN receives its parameters: by value below
+// 16384 (the hardware preloads the first words of the argument, which saves
+// latency on short workgroups), else as a pointer to the context's device copy
+// (DevParams::self), read field by field with scalar loads, which leaves the
+// registers to the transform (by value the largest kernels spill).
+template <int LOGN>
+struct ParamArg {
+    using type = DevParams;
+    __host__ __device__ static type of(const DevParams& p) { return p; }
+};
+template <>
+struct ParamArg<14> {
+    using type = const DevParams* __restrict__;
+    __host__ __device__ static const DevParams* of(const DevParams& p) { return p.self; }
+};
+__device__ __forceinline__ const DevParams& deref(const DevParams& p) { return p; }
+__device__ __forceinline__ const DevParams& deref(const DevParams* p) { return *p; }
+
 struct EncArgs {
     const double* slots;     // [batch][n_slots] (FROM_SLOTS)
     uint32_t n_slots;

@@ -15,7 +15,8 @@ using namespace split;
 
 template <int SCHEME, bool FROM_SLOTS, bool BGV = false>
 __global__ void __launch_bounds__(TS) __attribute__((amdgpu_waves_per_eu(4)))
-k_encrypt_split(DevParams p, EncArgs a) {
+k_encrypt_split(const DevParams* __restrict__ pp, EncArgs a) {
+    const DevParams& p = *pp;   // see ParamArg
     __shared__ u64 lds[LdsWords<NH>::value];
     __shared__ u64 tab[kCdtTab];
     const uint32_t t = threadIdx.x, b = blockIdx.x;
@@ -31,7 +32,8 @@ k_encrypt_split(DevParams p, EncArgs a) {
 // key generation, N = 32768 (integer arithmetic), one workgroup per modulus;
 // under BGV the key error is t e (Eq. 13)
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(TS) k_keygen_split(DevParams p, u64* sk, u64* sk_sh, u64* pk, u64* pk_sh) {
+__global__ void __launch_bounds__(TS) k_keygen_split(const DevParams* __restrict__ pp, u64* sk, u64* sk_sh, u64* pk, u64* pk_sh) {
+    const DevParams& p = *pp;   // see ParamArg
     __shared__ u64 lds[LdsWords<NH>::value];
     __shared__ u64 tab[kCdtTab];
     const uint32_t t = threadIdx.x, l = blockIdx.x;
@@ -78,7 +80,8 @@ __global__ void __launch_bounds__(TS) k_keygen_split(DevParams p, u64* sk, u64* 
     }
 }
 
-__global__ void __launch_bounds__(TS) k_decrypt_split(DevParams p, const u64* ct, u64* pt) {
+__global__ void __launch_bounds__(TS) k_decrypt_split(const DevParams* __restrict__ pp, const u64* ct, u64* pt) {
+    const DevParams& p = *pp;   // see ParamArg
     __shared__ u64 lds[LdsWords<NH>::value];
     const uint32_t t = threadIdx.x, l = blockIdx.x, b = blockIdx.y, L = p.L;
     const LimbConst lc = p.limbs[l];
@@ -93,7 +96,8 @@ __global__ void __launch_bounds__(TS) k_decrypt_split(DevParams p, const u64* ct
 }
 
 template <bool INV>
-__global__ void __launch_bounds__(TS) k_ntt_split(DevParams p, uint32_t limb, u64* poly) {
+__global__ void __launch_bounds__(TS) k_ntt_split(const DevParams* __restrict__ pp, uint32_t limb, u64* poly) {
+    const DevParams& p = *pp;   // see ParamArg
     __shared__ u64 lds[LdsWords<NH>::value];
     const uint32_t t = threadIdx.x;
     u64* x = poly + (size_t)blockIdx.x * NF;
@@ -123,7 +127,8 @@ __global__ void __launch_bounds__(TS) k_ntt_split(DevParams p, uint32_t limb, u6
     }
 }
 
-__global__ void __launch_bounds__(TS) k_encode_split(DevParams p, const double* slots, uint32_t n_slots, u64* pt) {
+__global__ void __launch_bounds__(TS) k_encode_split(const DevParams* __restrict__ pp, const double* slots, uint32_t n_slots, u64* pt) {
+    const DevParams& p = *pp;   // see ParamArg
     __shared__ u64 lds[LdsWords<NH>::value];
     const uint32_t t = threadIdx.x, b = blockIdx.x;
     long long mlo[RS], mhi[RS];
@@ -144,7 +149,8 @@ __global__ void __launch_bounds__(TS) k_encode_split(DevParams p, const double* 
 // odd-indexed halves are transformed separately (N/4 points each, roots
 // exp(+2 pi i / (N/4))), E kept in registers, then F[k] = E[k] + w^k O[k],
 // F[k + N/4] = E[k] - w^k O[k] with w = exp(+2 pi i / (N/2)); z_j = Re F[k_j] / Delta.
-__global__ void __launch_bounds__(TS) k_decode_split(DevParams p, const u64* pt, double* slots) {
+__global__ void __launch_bounds__(TS) k_decode_split(const DevParams* __restrict__ pp, const u64* pt, double* slots) {
+    const DevParams& p = *pp;   // see ParamArg
     constexpr int H = NF / 2, Q = H / 2, LOGH = 14, LOGQ = 13, PER = Q / TS;
     __shared__ u64 lds[LdsWords<NH>::value];
     C2* A = reinterpret_cast<C2*>(lds);
@@ -206,7 +212,7 @@ __global__ void __launch_bounds__(TS) k_decode_split(DevParams p, const u64* pt,
 // ---------------------------------------------------------------------------
 hipError_t launch_split_keygen(const DevParams& p, uint64_t* sk, uint64_t* sk_sh, uint64_t* pk, uint64_t* pk_sh,
                                hipStream_t s) {
-    hipLaunchKernelGGL(k_keygen_split, dim3(p.M), dim3(TS), 0, s, p, (u64*)sk, (u64*)sk_sh, (u64*)pk, (u64*)pk_sh);
+    hipLaunchKernelGGL(k_keygen_split, dim3(p.M), dim3(TS), 0, s, p.self, (u64*)sk, (u64*)sk_sh, (u64*)pk, (u64*)pk_sh);
     return hipGetLastError();
 }
 
@@ -217,40 +223,40 @@ hipError_t launch_split_encrypt(const DevParams& p, int scheme, bool from_slots,
     if (p.noise_t > 1) {            // BGV: integer plaintexts only
         if (from_slots) return hipErrorInvalidValue;
         if (scheme == ZINC_SCHEME_ZINC)
-            hipLaunchKernelGGL((k_encrypt_split<ZINC_SCHEME_ZINC, false, true>), dim3(batch), dim3(TS), 0, s, p, a);
-        else hipLaunchKernelGGL((k_encrypt_split<ZINC_SCHEME_VANILLA, false, true>), dim3(batch), dim3(TS), 0, s, p, a);
+            hipLaunchKernelGGL((k_encrypt_split<ZINC_SCHEME_ZINC, false, true>), dim3(batch), dim3(TS), 0, s, p.self, a);
+        else hipLaunchKernelGGL((k_encrypt_split<ZINC_SCHEME_VANILLA, false, true>), dim3(batch), dim3(TS), 0, s, p.self, a);
     } else if (scheme == ZINC_SCHEME_ZINC) {
-        if (from_slots) hipLaunchKernelGGL((k_encrypt_split<ZINC_SCHEME_ZINC, true>), dim3(batch), dim3(TS), 0, s, p, a);
-        else hipLaunchKernelGGL((k_encrypt_split<ZINC_SCHEME_ZINC, false>), dim3(batch), dim3(TS), 0, s, p, a);
+        if (from_slots) hipLaunchKernelGGL((k_encrypt_split<ZINC_SCHEME_ZINC, true>), dim3(batch), dim3(TS), 0, s, p.self, a);
+        else hipLaunchKernelGGL((k_encrypt_split<ZINC_SCHEME_ZINC, false>), dim3(batch), dim3(TS), 0, s, p.self, a);
     } else {
-        if (from_slots) hipLaunchKernelGGL((k_encrypt_split<ZINC_SCHEME_VANILLA, true>), dim3(batch), dim3(TS), 0, s, p, a);
-        else hipLaunchKernelGGL((k_encrypt_split<ZINC_SCHEME_VANILLA, false>), dim3(batch), dim3(TS), 0, s, p, a);
+        if (from_slots) hipLaunchKernelGGL((k_encrypt_split<ZINC_SCHEME_VANILLA, true>), dim3(batch), dim3(TS), 0, s, p.self, a);
+        else hipLaunchKernelGGL((k_encrypt_split<ZINC_SCHEME_VANILLA, false>), dim3(batch), dim3(TS), 0, s, p.self, a);
     }
     return hipGetLastError();
 }
 
 hipError_t launch_split_encode(const DevParams& p, const double* slots, uint32_t n_slots, uint32_t batch,
                                uint64_t* pt, hipStream_t s) {
-    hipLaunchKernelGGL(k_encode_split, dim3(batch), dim3(TS), 0, s, p, slots, n_slots, (u64*)pt);
+    hipLaunchKernelGGL(k_encode_split, dim3(batch), dim3(TS), 0, s, p.self, slots, n_slots, (u64*)pt);
     return hipGetLastError();
 }
 
 hipError_t launch_split_decrypt(const DevParams& p, const uint64_t* ct, uint32_t batch, uint64_t* pt,
                                 hipStream_t s) {
-    hipLaunchKernelGGL(k_decrypt_split, dim3(p.L, batch), dim3(TS), 0, s, p, (const u64*)ct, (u64*)pt);
+    hipLaunchKernelGGL(k_decrypt_split, dim3(p.L, batch), dim3(TS), 0, s, p.self, (const u64*)ct, (u64*)pt);
     return hipGetLastError();
 }
 
 hipError_t launch_split_decode(const DevParams& p, const uint64_t* pt, uint32_t batch, double* slots,
                                hipStream_t s) {
-    hipLaunchKernelGGL(k_decode_split, dim3(batch), dim3(TS), 0, s, p, (const u64*)pt, slots);
+    hipLaunchKernelGGL(k_decode_split, dim3(batch), dim3(TS), 0, s, p.self, (const u64*)pt, slots);
     return hipGetLastError();
 }
 
 hipError_t launch_split_ntt(const DevParams& p, bool inverse, uint32_t limb, uint64_t* poly, uint32_t n_polys,
                             hipStream_t s) {
-    if (inverse) hipLaunchKernelGGL((k_ntt_split<true>), dim3(n_polys), dim3(TS), 0, s, p, limb, (u64*)poly);
-    else hipLaunchKernelGGL((k_ntt_split<false>), dim3(n_polys), dim3(TS), 0, s, p, limb, (u64*)poly);
+    if (inverse) hipLaunchKernelGGL((k_ntt_split<true>), dim3(n_polys), dim3(TS), 0, s, p.self, limb, (u64*)poly);
+    else hipLaunchKernelGGL((k_ntt_split<false>), dim3(n_polys), dim3(TS), 0, s, p.self, limb, (u64*)poly);
     return hipGetLastError();
 }
 

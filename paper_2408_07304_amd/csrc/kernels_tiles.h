@@ -15,7 +15,8 @@ namespace {  // each including translation unit has its own copy
 // one ciphertext already bounds the workgroups per CU).
 template <class G, int SCHEME, int WPE, bool REG>
 __global__ void __launch_bounds__(G::T) __attribute__((amdgpu_waves_per_eu(WPE)))
-k_encrypt_tile(DevParams p, EncArgs a) {
+k_encrypt_tile(typename ParamArg<G::LOGN>::type pa, EncArgs a) {
+    const DevParams& p = deref(pa);
     constexpr int N = G::N;
     __shared__ u64 lds[LdsWords<N>::value];
     __shared__ u64 tab[kCdtTab];
@@ -30,7 +31,7 @@ k_encrypt_tile(DevParams p, EncArgs a) {
 
 template <class G, int SCHEME, int WPE, bool REG>
 hipError_t launch_tile(const DevParams& p, const EncArgs& a, uint32_t batch, hipStream_t s) {
-    hipLaunchKernelGGL((k_encrypt_tile<G, SCHEME, WPE, REG>), dim3(batch), dim3(G::T), 0, s, p, a);
+    hipLaunchKernelGGL((k_encrypt_tile<G, SCHEME, WPE, REG>), dim3(batch), dim3(G::T), 0, s, ParamArg<G::LOGN>::of(p), a);
     return hipGetLastError();
 }
 

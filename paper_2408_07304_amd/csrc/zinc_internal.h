@@ -66,6 +66,12 @@ struct DevParams {
     const uint64_t* pkp;          // [2][L][N]  pk_j p^-1 on the data limbs (special-prime vanilla)
     const uint64_t* pkp_sh;       // [2][L][N]  Shoup companions
     uint32_t* err;                // sticky device error flags
+    // This struct's copy in device memory.  The largest kernels (ring degree
+    // 16384 and the split 32768 ones) read their parameters through it, field
+    // by field with scalar loads, which frees registers (by value the split
+    // kernels spill); the others take the kernel argument, whose first words
+    // the hardware preloads, which saves latency on short workgroups.
+    const DevParams* self;
 };
 
 // Per-call constants of the BFV integer encoding and decoding for plaintext

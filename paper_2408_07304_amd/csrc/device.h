@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "zinc_internal.h"
 
 namespace zinc {
@@ -334,11 +336,39 @@ __device__ __forceinline__ auto load_tw(const T* p) {
     else return load_pair(p);
 }
 
+// The twiddles of the first stage of forward pass P, requested ahead of the
+// exchange into the pass's layout so that their latency overlaps the LDS
+// round trip (and, on the FP64 path, the optional reduction's branch, behind
+// which no load of the pass could otherwise start).  w[c] is set for the
+// registers c that start a butterfly of that stage; registers sharing a
+// twiddle share one load.  Only for 16 coefficients per thread in workgroups
+// of at most 512 threads: measured 2 % faster at N = 8192; with 1024 threads
+// (N = 16384) the registers held across the exchange spill, and with 8 per
+// thread it gains nothing.
+template <class G>
+__host__ __device__ constexpr bool preload_tw() { return G::R == 16 && G::T <= 512; }
+template <class G, int P, class T>
+struct FirstTw {
+    typename std::conditional<std::is_same<T, double>::value, f64x2, u64x2>::type w[G::R];
+};
+template <class G, int P, class T>
+__device__ __forceinline__ FirstTw<G, P, T> first_tw(const T* __restrict__ tw, uint32_t toff, uint32_t smul,
+                                                      uint32_t t) {
+    constexpr int b = G::K(P) - 1;
+    const uint32_t tp = tw_tpart<G, P>(t);
+    FirstTw<G, P, T> r;
+#pragma unroll
+    for (int c = 0; c < G::R; ++c)
+        if (!(c & (1 << b))) r.w[c] = load_tw<G, P>(tw + toff + 2 * tw_index<G, P>(tp, c, b, smul));
+    return r;
+}
+
 // ---- integer path (any modulus below 2^60): Shoup butterflies, lazy bounds ----
 
 template <class G, int P>
 __device__ __forceinline__ void fwd_pass(u64 (&v)[G::R], uint32_t t, const u64* __restrict__ tw,
-                                         uint32_t toff, uint32_t smul, u64 q, u64 q2) {
+                                         uint32_t toff, uint32_t smul, u64 q, u64 q2,
+                                         const FirstTw<G, P, u64>* w0 = nullptr) {
     constexpr int K = G::K(P);
     const uint32_t tp = tw_tpart<G, P>(t);
     const u64 q8 = q << 3;
@@ -350,7 +380,7 @@ __device__ __forceinline__ void fwd_pass(u64 (&v)[G::R], uint32_t t, const u64* 
         for (int c = 0; c < G::R; ++c) {
             if (c & (1 << b)) continue;
             const uint32_t ti = toff + 2 * tw_index<G, P>(tp, c, b, smul);
-            const u64x2 w = load_tw<G, P>(tw + ti);
+            const u64x2 w = w0 && i == 0 ? w0->w[c] : load_tw<G, P>(tw + ti);
             if (fwd_reduce(J0 + i)) ct_bfly<true>(v[c], v[c | (1 << b)], w.x, w.y, q, q2, q8);
             else ct_bfly<false>(v[c], v[c | (1 << b)], w.x, w.y, q, q2, q8);
         }
@@ -378,8 +408,14 @@ template <class G, int P>
 __device__ __forceinline__ void fwd_rest(u64 (&v)[G::R], u64* lds, const u64* __restrict__ tw, uint32_t toff,
                                          uint32_t smul, u64 q, u64 q2, uint32_t t) {
     if constexpr (P < G::NPASS) {
-        exchange<G, P - 1, P>(lds, v, t);
-        fwd_pass<G, P>(v, t, tw, toff, smul, q, q2);
+        if constexpr (preload_tw<G>()) {
+            const auto w0 = first_tw<G, P>(tw, toff, smul, t);
+            exchange<G, P - 1, P>(lds, v, t);
+            fwd_pass<G, P>(v, t, tw, toff, smul, q, q2, &w0);
+        } else {
+            exchange<G, P - 1, P>(lds, v, t);
+            fwd_pass<G, P>(v, t, tw, toff, smul, q, q2);
+        }
         fwd_rest<G, P + 1>(v, lds, tw, toff, smul, q, q2, t);
     }
 }
@@ -487,7 +523,8 @@ __device__ __forceinline__ double u64_to_fp(u64 x) {
 
 template <class G, int P>
 __device__ __forceinline__ void fwd_pass_fp(double (&v)[G::R], uint32_t t, const double* __restrict__ tw,
-                                            uint32_t toff, uint32_t smul, double q, double qinv, bool reduce) {
+                                            uint32_t toff, uint32_t smul, double q, double qinv, bool reduce,
+                                            const FirstTw<G, P, double>* w0 = nullptr) {
     constexpr int K = G::K(P);
     const uint32_t tp = tw_tpart<G, P>(t);
     if (reduce) {
@@ -501,7 +538,7 @@ __device__ __forceinline__ void fwd_pass_fp(double (&v)[G::R], uint32_t t, const
         for (int c = 0; c < G::R; ++c) {
             if (c & (1 << b)) continue;
             const uint32_t ti = toff + 2 * tw_index<G, P>(tp, c, b, smul);
-            const f64x2 w = load_tw<G, P>(tw + ti);
+            const f64x2 w = w0 && i == 0 ? w0->w[c] : load_tw<G, P>(tw + ti);
             ct_bfly_fp(v[c], v[c | (1 << b)], w.x, w.y, q);
         }
     }
@@ -512,8 +549,14 @@ __device__ __forceinline__ void fwd_rest_fp(double (&v)[G::R], double* lds, cons
                                             uint32_t toff, uint32_t smul, double q, double qinv, bool reduce,
                                             uint32_t t) {
     if constexpr (P < G::NPASS) {
-        exchange<G, P - 1, P>(lds, v, t);
-        fwd_pass_fp<G, P>(v, t, tw, toff, smul, q, qinv, reduce);
+        if constexpr (preload_tw<G>()) {
+            const auto w0 = first_tw<G, P>(tw, toff, smul, t);
+            exchange<G, P - 1, P>(lds, v, t);
+            fwd_pass_fp<G, P>(v, t, tw, toff, smul, q, qinv, reduce, &w0);
+        } else {
+            exchange<G, P - 1, P>(lds, v, t);
+            fwd_pass_fp<G, P>(v, t, tw, toff, smul, q, qinv, reduce);
+        }
         fwd_rest_fp<G, P + 1>(v, lds, tw, toff, smul, q, qinv, reduce, t);
     }
 }

@@ -683,47 +683,84 @@ __device__ __forceinline__ void fft_dit(C2* A, const double* __restrict__ fft_tw
 __host__ __device__ constexpr uint32_t padc(uint32_t i) { return i + (i >> 4); }
 __host__ __device__ constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x >> 1); }
 
+// Index bits of register e of thread t in pass P of fft_reg_pass.
+template <int LOGH, int LOGT, int P>
+struct FftPass {
+    static constexpr int LOGR = LOGH - LOGT, R = 1 << LOGR;
+    static constexpr int B = P * LOGR, K = (LOGH - B < LOGR) ? LOGH - B : LOGR;
+    __device__ static __forceinline__ uint32_t idx(uint32_t t, int e) {
+        const uint32_t c = (uint32_t)e & ((1u << K) - 1u), rest = t | ((uint32_t)(e >> K) << LOGT);
+        return (rest & ((1u << B) - 1u)) | (c << B) | ((rest >> B) << (B + K));
+    }
+};
+
+// The twiddles of pass P, w[k][e] for stage k and the registers e that start
+// a butterfly; they depend on the thread index only, so they are requested
+// before the barrier that ends the previous pass and arrive while it waits.
+template <int LOGH, int LOGT, int SIGN, int LOGTAB, int P>
+struct FftTw {
+    using F = FftPass<LOGH, LOGT, P>;
+    C2 w[F::K > 0 ? F::K : 1][F::R];
+};
+template <int LOGH, int LOGT, int SIGN, int LOGTAB, int P>
+__device__ __forceinline__ FftTw<LOGH, LOGT, SIGN, LOGTAB, P> fft_pass_tw(const double* __restrict__ fft_tw,
+                                                                          uint32_t t) {
+    using F = FftPass<LOGH, LOGT, P>;
+    FftTw<LOGH, LOGT, SIGN, LOGTAB, P> r;
+#pragma unroll
+    for (int k = 0; k < F::K; ++k) {
+        const int s = F::B + k + 1;
+        const uint32_t half = 1u << (s - 1);
+#pragma unroll
+        for (int e = 0; e < F::R; ++e) {
+            if (e & (1 << k)) continue;
+            const uint32_t ti = (F::idx(t, e) & (half - 1u)) << (LOGTAB - s);   // < 2^(LOGTAB-1) for any t
+            const f64x2 w = load_pair(fft_tw + 2 * ti);
+            r.w[k][e] = C2{w.x, SIGN > 0 ? -w.y : w.y};
+        }
+    }
+    return r;
+}
+
 template <int LOGH, int LOGT, int SIGN, int LOGTAB, int P, bool PARTIAL>
-__device__ __forceinline__ void fft_reg_pass(C2* A, const double* __restrict__ fft_tw, uint32_t t) {
-    constexpr int LOGR = LOGH - LOGT, R = 1 << LOGR;
-    constexpr int B = P * LOGR, K = (LOGH - B < LOGR) ? LOGH - B : LOGR;
-    if constexpr (B < LOGH) {
-        if (!PARTIAL || t < (1u << LOGT)) {
-            uint32_t idx[R];
+__device__ __forceinline__ void fft_reg_pass(C2* A, const double* __restrict__ fft_tw, uint32_t t,
+                                             const FftTw<LOGH, LOGT, SIGN, LOGTAB, P>& tw) {
+    using F = FftPass<LOGH, LOGT, P>;
+    constexpr int R = F::R, K = F::K;
+    if constexpr (F::B < LOGH) {
+        const bool active = !PARTIAL || t < (1u << LOGT);
+        if (active) {
             C2 v[R];
 #pragma unroll
-            for (int e = 0; e < R; ++e) {
-                const uint32_t c = (uint32_t)e & ((1u << K) - 1u), rest = t | ((uint32_t)(e >> K) << LOGT);
-                idx[e] = (rest & ((1u << B) - 1u)) | (c << B) | ((rest >> B) << (B + K));
-                v[e] = A[padc(idx[e])];
-            }
+            for (int e = 0; e < R; ++e) v[e] = A[padc(F::idx(t, e))];
 #pragma unroll
             for (int k = 0; k < K; ++k) {
-                const int s = B + k + 1;
-                const uint32_t half = 1u << (s - 1);
 #pragma unroll
                 for (int e = 0; e < R; ++e) {
                     if (e & (1 << k)) continue;
-                    const uint32_t ti = (idx[e] & (half - 1u)) << (LOGTAB - s);
-                    C2 w{fft_tw[2 * ti], fft_tw[2 * ti + 1]};
-                    if (SIGN > 0) w.y = -w.y;
-                    const C2 a = v[e], bw = cmul(v[e | (1 << k)], w);
+                    const C2 a = v[e], bw = cmul(v[e | (1 << k)], tw.w[k][e]);
                     v[e] = C2{a.x + bw.x, a.y + bw.y};
                     v[e | (1 << k)] = C2{a.x - bw.x, a.y - bw.y};
                 }
             }
 #pragma unroll
-            for (int e = 0; e < R; ++e) A[padc(idx[e])] = v[e];
+            for (int e = 0; e < R; ++e) A[padc(F::idx(t, e))] = v[e];
         }
+        FftTw<LOGH, LOGT, SIGN, LOGTAB, P + 1> next;
+        if constexpr (F::B + F::LOGR < LOGH)
+            if (active) next = fft_pass_tw<LOGH, LOGT, SIGN, LOGTAB, P + 1>(fft_tw, t);
         __syncthreads();
-        fft_reg_pass<LOGH, LOGT, SIGN, LOGTAB, P + 1, PARTIAL>(A, fft_tw, t);
+        fft_reg_pass<LOGH, LOGT, SIGN, LOGTAB, P + 1, PARTIAL>(A, fft_tw, t, next);
     }
 }
 
 template <int LOGH, int T, int SIGN, int LOGTAB = LOGH, bool PARTIAL = false>
 __device__ __forceinline__ void fft_dit_reg(C2* A, const double* __restrict__ fft_tw, uint32_t t) {
     static_assert((1 << ilog2(T)) == T && ilog2(T) < LOGH, "T must be a power of two below 2^LOGH");
-    fft_reg_pass<LOGH, ilog2(T), SIGN, LOGTAB, 0, PARTIAL>(A, fft_tw, t);
+    constexpr int LOGT = ilog2(T);
+    FftTw<LOGH, LOGT, SIGN, LOGTAB, 0> tw0;
+    if (!PARTIAL || t < (1u << LOGT)) tw0 = fft_pass_tw<LOGH, LOGT, SIGN, LOGTAB, 0>(fft_tw, t);
+    fft_reg_pass<LOGH, LOGT, SIGN, LOGTAB, 0, PARTIAL>(A, fft_tw, t, tw0);
 }
 
 // CKKS encoding of one slot vector into the integer coefficients m held in

@@ -188,6 +188,55 @@ def test_encode_exact_at_moderate_magnitude(name):
         assert mism <= 2, (name, i, mism)
 
 
+SPARSE_COUNTS = (1, 2, 3, 4, 5)     # up to three values: direct sum over the slots; four, five: the transform
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_encode_sparse_slot_vectors(name):
+    """Slot vectors of at most three values skip the transform: each entry of
+    the transformed vector is summed term by term over the given slots.
+    Vectors of one to five values (up to the threshold and past it) against the
+    oracle's encoding under check_encoding's rules, at unit magnitude and with
+    coefficients of rms about min(2^32, q_0/64), where the tie window is far
+    below the rounding grid."""
+    c = gpu_ctx(name)
+    P = oracle_keys(name)[0]
+    rng = np.random.default_rng(29)
+    for n in SPARSE_COUNTS:
+        z = rng.uniform(-1, 1, size=(2, n))
+        z[1] *= min(2.0 ** 32, P.moduli[0] / 64) * P.n / (2.0 * P.scale * np.sqrt(n))
+        out = empty_u64(2, P.L, P.n)
+        say(f"{name} encode {n} slot values")
+        c.encode(to_dev(z), out)
+        got = from_dev(out)
+        for i in range(2):
+            m, fr = oracle.encode(P, z[i])
+            g = centred(got[i, 0], P.moduli[0])
+            for l in range(1, P.L):
+                assert np.array_equal(got[i, l], oracle.to_rns(P, g, P.L)[l]), (n, i, l)
+            check_encoding(P.n, g, m, fr, (name, n, i))
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("name", NAMES)
+def test_fused_sparse_rows_against_oracle(name, scheme):
+    """Fused encryption of rows of one, three and four values (Table 2's rows
+    hold 1 to 16) against the oracle's Algorithm 1 / Eq. 8 of the same slots."""
+    c = gpu_ctx(name)
+    P, sh, pk, zero = oracle_keys(name)
+    key = zero if scheme == zinc.ZINC_SCHEME_ZINC else pk
+    rng = np.random.default_rng(31 + scheme)
+    for n in (1, 3, 4):
+        z = rng.uniform(-1, 1, size=(3, n))
+        cid = [5 * n, 5 * n + 1, 2 ** 40 + n]
+        out = empty_u64(3, 2, P.L, P.n)
+        say(f"{name} scheme={scheme} fused rows of {n} values")
+        c.encrypt_slots(scheme, to_dev(z), ids(cid), out)
+        got = from_dev(out)
+        for i in range(3):
+            check_fused(c, P, scheme, key, z[i], cid[i], got[i], (name, scheme, n, i))
+
+
 @pytest.mark.parametrize("scheme", SCHEMES)
 @pytest.mark.parametrize("name", NAMES)
 def test_fused_equals_encode_then_encrypt(name, scheme):

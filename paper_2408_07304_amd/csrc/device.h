@@ -724,11 +724,11 @@ __device__ __forceinline__ FftTw<LOGH, LOGT, SIGN, LOGTAB, P> fft_pass_tw(const 
 
 template <int LOGH, int LOGT, int SIGN, int LOGTAB, int P, bool PARTIAL>
 __device__ __forceinline__ void fft_reg_pass(C2* A, const double* __restrict__ fft_tw, uint32_t t,
-                                             const FftTw<LOGH, LOGT, SIGN, LOGTAB, P>& tw, bool work) {
+                                             const FftTw<LOGH, LOGT, SIGN, LOGTAB, P>& tw) {
     using F = FftPass<LOGH, LOGT, P>;
     constexpr int R = F::R, K = F::K;
     if constexpr (F::B < LOGH) {
-        const bool active = work && (!PARTIAL || t < (1u << LOGT));
+        const bool active = !PARTIAL || t < (1u << LOGT);
         if (active) {
             C2 v[R];
 #pragma unroll
@@ -750,47 +750,17 @@ __device__ __forceinline__ void fft_reg_pass(C2* A, const double* __restrict__ f
         if constexpr (F::B + F::LOGR < LOGH)
             if (active) next = fft_pass_tw<LOGH, LOGT, SIGN, LOGTAB, P + 1>(fft_tw, t);
         __syncthreads();
-        fft_reg_pass<LOGH, LOGT, SIGN, LOGTAB, P + 1, PARTIAL>(A, fft_tw, t, next, work);
+        fft_reg_pass<LOGH, LOGT, SIGN, LOGTAB, P + 1, PARTIAL>(A, fft_tw, t, next);
     }
 }
 
-// work = false (the same value in every thread of the workgroup): every
-// barrier is still reached, no point is transformed.
 template <int LOGH, int T, int SIGN, int LOGTAB = LOGH, bool PARTIAL = false>
-__device__ __forceinline__ void fft_dit_reg(C2* A, const double* __restrict__ fft_tw, uint32_t t, bool work = true) {
+__device__ __forceinline__ void fft_dit_reg(C2* A, const double* __restrict__ fft_tw, uint32_t t) {
     static_assert((1 << ilog2(T)) == T && ilog2(T) < LOGH, "T must be a power of two below 2^LOGH");
     constexpr int LOGT = ilog2(T);
     FftTw<LOGH, LOGT, SIGN, LOGTAB, 0> tw0;
-    if (work && (!PARTIAL || t < (1u << LOGT))) tw0 = fft_pass_tw<LOGH, LOGT, SIGN, LOGTAB, 0>(fft_tw, t);
-    fft_reg_pass<LOGH, LOGT, SIGN, LOGTAB, 0, PARTIAL>(A, fft_tw, t, tw0, work);
-}
-
-// Slot vectors with at most kSparseSlots values skip the transform: entry i
-// of the N/2-point transform of the real vector Z (Delta z_j at position k_j)
-// is F[i] = sum_j Delta z_j exp(-2 pi i k_j i / (N/2)), evaluated term by term
-// from the root table (exp(-2 pi i x / (N/2)) for x < N/4, the negation of
-// the entry x - N/4 above).  k_j is read back from slot_pos, which holds
-// brv(k_j).  Measured on 1024 rows, encoding alone: one value 16 % (N = 8192)
-// and 7 % (N = 32768, where writing the residues dominates) faster than the
-// transform, three values 5 % and 3 %, four values 1 % slower.
-constexpr uint32_t kSparseSlots = 3;
-template <int LOGH>
-__device__ __forceinline__ C2 sparse_transform(const DevParams& p, const double* __restrict__ z, uint32_t n_slots,
-                                               uint32_t i) {
-    constexpr uint32_t H = 1u << LOGH;
-    C2 F{0.0, 0.0};
-#pragma unroll
-    for (uint32_t j = 0; j < kSparseSlots; ++j) {
-        if (j >= n_slots) break;
-        const double a = p.scale * z[j];
-        const uint32_t k = __brev(p.slot_pos[j]) >> (32 - LOGH);
-        const uint32_t x = (k * i) & (H - 1), xs = x & (H / 2 - 1);
-        const f64x2 w = load_pair(p.fft_tw + 2 * xs);
-        const double sg = x >= H / 2 ? -a : a;
-        F.x += sg * w.x;
-        F.y += sg * w.y;
-    }
-    return F;
+    if (!PARTIAL || t < (1u << LOGT)) tw0 = fft_pass_tw<LOGH, LOGT, SIGN, LOGTAB, 0>(fft_tw, t);
+    fft_reg_pass<LOGH, LOGT, SIGN, LOGTAB, 0, PARTIAL>(A, fft_tw, t, tw0);
 }
 
 // CKKS encoding of one slot vector into the integer coefficients m held in
@@ -812,17 +782,14 @@ __device__ __forceinline__ void encode_p0(long long (&m)[G::R], u64* lds, const 
     constexpr int TF = Q / 8 < G::T ? Q / 8 : G::T;
     double* Ad = reinterpret_cast<double*>(lds);
     C2* A = reinterpret_cast<C2*>(lds);
-    const bool dense = n_slots > kSparseSlots;          // the same in every thread
     __syncthreads();
-    if (dense) {
-        for (uint32_t j = t; j < (uint32_t)H; j += G::T) {
-            const double val = j < n_slots ? p.scale * z[j] : 0.0;
-            const uint32_t bk = p.slot_pos[j];               // brv_{log H}(k_j)
-            Ad[2 * padc(bk & (Q - 1)) + (bk >> (LOGH - 1))] = val;   // Y[k_j / 2] gets Z[k_j] in Re or Im
-        }
+    for (uint32_t j = t; j < (uint32_t)H; j += G::T) {
+        const double val = j < n_slots ? p.scale * z[j] : 0.0;
+        const uint32_t bk = p.slot_pos[j];               // brv_{log H}(k_j)
+        Ad[2 * padc(bk & (Q - 1)) + (bk >> (LOGH - 1))] = val;   // Y[k_j / 2] gets Z[k_j] in Re or Im
     }
     __syncthreads();
-    fft_dit_reg<LOGQ, TF, -1, LOGH, (TF < G::T)>(A, p.fft_tw, t, dense);
+    fft_dit_reg<LOGQ, TF, -1, LOGH, (TF < G::T)>(A, p.fft_tw, t);
     const double f = 2.0 / (double)G::N;
     constexpr int TOP = 1 << (G::K(0) - 1);
     const uint32_t tp = G::tpart(0, t);
@@ -838,36 +805,86 @@ __device__ __forceinline__ void encode_p0(long long (&m)[G::R], u64* lds, const 
         }
         return (long long)x;
     };
-    // coefficients i and i + N/2 from entry F of the transform
-    auto finish = [&](int c, uint32_t i, C2 F) {
+#pragma unroll
+    for (int c = 0; c < G::R; ++c) {
+        if (c & TOP) continue;
+        const uint32_t i = tp | G::cpart(0, c);         // < H
+        const uint32_t m1 = i & (Q - 1), m2 = (Q - m1) & (Q - 1);
+        const C2 y1 = A[padc(m1)], y2 = A[padc(m2)];
+        const C2 ev{0.5 * (y1.x + y2.x), 0.5 * (y1.y - y2.y)};     // (Y1 + conj Y2) / 2
+        const C2 od{0.5 * (y1.y + y2.y), -0.5 * (y1.x - y2.x)};    // (Y1 - conj Y2) / 2i
+        C2 w{p.fft_tw[2 * (i & (H / 2 - 1))], p.fft_tw[2 * (i & (H / 2 - 1)) + 1]};
+        if (i >= (uint32_t)(H / 2)) {
+            w.x = -w.x;
+            w.y = -w.y;
+        }
+        const C2 o = cmul(w, od);
+        const C2 F{ev.x + o.x, ev.y + o.y};
         const C2 r = cmul(F, C2{p.twist[2 * i], p.twist[2 * i + 1]});
         m[c] = to_int(r.x * f);
         m[c | TOP] = to_int(r.y * f);
-    };
-    if (dense) {
+    }
+    if (bad) atomicOr(p.err, 1u);
+}
+
+// Encoding of slot vectors with at most kSparseSlots values, for the encoding
+// kernels: entry i of the N/2-point transform of the real vector Z (Delta z_j
+// at position k_j) is F[i] = sum_j Delta z_j exp(-2 pi i k_j i / (N/2)),
+// evaluated term by term from the root table (exp(-2 pi i x / (N/2)) for
+// x < N/4, the negation of the entry x - N/4 above; k_j from slot_pos, which
+// holds brv(k_j)); no LDS, no barriers.  Measured on 1024 rows: one value
+// 23 % (N = 8192) and 8 % (N = 32768, where writing the residues dominates)
+// faster than the transform, three values 9 % and 2 %; with four values the
+// transform was as fast.  The fused encryption kernels keep the transform for
+// every vector: there the encoding is a small share of the launch, and the
+// extra code cost registers (scratch spills in the split and plan kernels).
+constexpr uint32_t kSparseSlots = 3;
+template <int LOGH>
+__device__ __forceinline__ C2 sparse_transform(const DevParams& p, const double* __restrict__ z, uint32_t n_slots,
+                                               uint32_t i) {
+    constexpr uint32_t H = 1u << LOGH;
+    C2 F{0.0, 0.0};
 #pragma unroll
-        for (int c = 0; c < G::R; ++c) {
-            if (c & TOP) continue;
-            const uint32_t i = tp | G::cpart(0, c);         // < H
-            const uint32_t m1 = i & (Q - 1), m2 = (Q - m1) & (Q - 1);
-            const C2 y1 = A[padc(m1)], y2 = A[padc(m2)];
-            const C2 ev{0.5 * (y1.x + y2.x), 0.5 * (y1.y - y2.y)};     // (Y1 + conj Y2) / 2
-            const C2 od{0.5 * (y1.y + y2.y), -0.5 * (y1.x - y2.x)};    // (Y1 - conj Y2) / 2i
-            C2 w{p.fft_tw[2 * (i & (H / 2 - 1))], p.fft_tw[2 * (i & (H / 2 - 1)) + 1]};
-            if (i >= (uint32_t)(H / 2)) {
-                w.x = -w.x;
-                w.y = -w.y;
-            }
-            const C2 o = cmul(w, od);
-            finish(c, i, C2{ev.x + o.x, ev.y + o.y});
-        }
-    } else {
-#pragma unroll 1
-        for (int c = 0; c < G::R; ++c) {
-            if (c & TOP) continue;
-            const uint32_t i = tp | G::cpart(0, c);
-            finish(c, i, sparse_transform<LOGH>(p, z, n_slots, i));
-        }
+    for (uint32_t j = 0; j < kSparseSlots; ++j) {
+        if (j >= n_slots) break;
+        const double a = p.scale * z[j];
+        const uint32_t k = __brev(p.slot_pos[j]) >> (32 - LOGH);
+        const uint32_t x = (k * i) & (H - 1), xs = x & (H / 2 - 1);
+        const f64x2 w = load_pair(p.fft_tw + 2 * xs);
+        const double sg = x >= H / 2 ? -a : a;
+        F.x += sg * w.x;
+        F.y += sg * w.y;
+    }
+    return F;
+}
+
+// Coefficients i and i + N/2 of the encoding from entry F[i] of the
+// transform: twist by zeta^-i, scale by 2/N, round half to even; false when
+// a value is out of range (|x| >= 2^62 or NaN), which then encodes as 0.
+__device__ __forceinline__ bool encode_pair(const DevParams& p, uint32_t i, C2 F, double f, long long& lo,
+                                            long long& hi) {
+    const C2 r = cmul(F, C2{p.twist[2 * i], p.twist[2 * i + 1]});
+    const double xl = __builtin_rint(r.x * f), xh = __builtin_rint(r.y * f);
+    const bool okl = __builtin_fabs(xl) < 4611686018427387904.0, okh = __builtin_fabs(xh) < 4611686018427387904.0;
+    lo = okl ? (long long)xl : 0;
+    hi = okh ? (long long)xh : 0;
+    return okl && okh;
+}
+
+// encode_p0's result for a vector of at most kSparseSlots values.
+template <class G>
+__device__ __forceinline__ void encode_sparse_p0(long long (&m)[G::R], const DevParams& p,
+                                                 const double* __restrict__ z, uint32_t n_slots, uint32_t t) {
+    constexpr int LOGH = G::LOGN - 1;
+    constexpr int TOP = 1 << (G::K(0) - 1);
+    const double f = 2.0 / (double)G::N;
+    const uint32_t tp = G::tpart(0, t);
+    bool bad = false;
+#pragma unroll
+    for (int c = 0; c < G::R; ++c) {
+        if (c & TOP) continue;
+        const uint32_t i = tp | G::cpart(0, c);         // < N/2
+        bad |= !encode_pair(p, i, sparse_transform<LOGH>(p, z, n_slots, i), f, m[c], m[c | TOP]);
     }
     if (bad) atomicOr(p.err, 1u);
 }

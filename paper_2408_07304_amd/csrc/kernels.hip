@@ -100,7 +100,9 @@ __global__ void __launch_bounds__(Cfg<LOGN>::G::T) k_encode(DevParams p, const d
     __shared__ u64 lds[LdsWords<N>::value];
     const uint32_t t = threadIdx.x, b = blockIdx.x;
     long long m[R];
-    encode_p0<G>(m, lds, p, slots + (size_t)b * n_slots, n_slots, t);
+    // n_slots is the same in every workgroup: no barrier is skipped by some threads only
+    if (n_slots <= kSparseSlots) encode_sparse_p0<G>(m, p, slots + (size_t)b * n_slots, n_slots, t);
+    else encode_p0<G>(m, lds, p, slots + (size_t)b * n_slots, n_slots, t);
     const uint32_t tp0 = G::tpart(0, t);
     for (uint32_t l = 0; l < p.L; ++l) {
         const LimbConst lc = p.limbs[l];

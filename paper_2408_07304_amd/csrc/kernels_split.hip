@@ -132,7 +132,9 @@ __global__ void __launch_bounds__(TS) k_encode_split(const DevParams* __restrict
     __shared__ u64 lds[LdsWords<NH>::value];
     const uint32_t t = threadIdx.x, b = blockIdx.x;
     long long mlo[RS], mhi[RS];
-    encode_split(mlo, mhi, lds, p, slots + (size_t)b * n_slots, n_slots, t);
+    // n_slots is the same in every workgroup: no barrier is skipped by some threads only
+    if (n_slots <= kSparseSlots) encode_sparse_split(mlo, mhi, p, slots + (size_t)b * n_slots, n_slots, t);
+    else encode_split(mlo, mhi, lds, p, slots + (size_t)b * n_slots, n_slots, t);
     const uint32_t tp0 = GS::tpart(0, t);
     for (uint32_t l = 0; l < p.L; ++l) {
         const LimbConst lc = p.limbs[l];

@@ -72,47 +72,49 @@ __device__ __forceinline__ void encode_split(long long (&mlo)[RS], long long (&m
     constexpr int H = NF / 2, Q = H / 2, LOGH = 14, LOGQ = 13;
     double* Ad = reinterpret_cast<double*>(lds);
     C2* A = reinterpret_cast<C2*>(lds);
-    const bool dense = n_slots > kSparseSlots;          // the same in every thread
     __syncthreads();
-    if (dense) {
-        for (uint32_t j = t; j < (uint32_t)H; j += TS) {
-            const double val = j < n_slots ? p.scale * z[j] : 0.0;
-            const uint32_t bk = p.slot_pos[j];               // brv_{log H}(k_j)
-            Ad[2 * padc(bk & (Q - 1)) + (bk >> (LOGH - 1))] = val;   // Y[k_j / 2] gets Z[k_j] in Re or Im
-        }
+    for (uint32_t j = t; j < (uint32_t)H; j += TS) {
+        const double val = j < n_slots ? p.scale * z[j] : 0.0;
+        const uint32_t bk = p.slot_pos[j];               // brv_{log H}(k_j)
+        Ad[2 * padc(bk & (Q - 1)) + (bk >> (LOGH - 1))] = val;   // Y[k_j / 2] gets Z[k_j] in Re or Im
     }
     __syncthreads();
-    fft_dit_reg<LOGQ, TS, -1, LOGH>(A, p.fft_tw, t, dense);
+    fft_dit_reg<LOGQ, TS, -1, LOGH>(A, p.fft_tw, t);
     const double f = 2.0 / (double)NF;
     const uint32_t tp0 = GS::tpart(0, t);
     bool bad = false;
-    auto finish = [&](int c, uint32_t i, C2 F) {
+#pragma unroll
+    for (int c = 0; c < RS; ++c) {
+        const uint32_t i = jp(tp0, c);                   // < H
+        const uint32_t m1 = i & (Q - 1), m2 = (Q - m1) & (Q - 1);
+        const C2 y1 = A[padc(m1)], y2 = A[padc(m2)];
+        const C2 ev{0.5 * (y1.x + y2.x), 0.5 * (y1.y - y2.y)};     // (Y1 + conj Y2) / 2
+        const C2 od{0.5 * (y1.y + y2.y), -0.5 * (y1.x - y2.x)};    // (Y1 - conj Y2) / 2i
+        C2 w{p.fft_tw[2 * (i & (H / 2 - 1))], p.fft_tw[2 * (i & (H / 2 - 1)) + 1]};
+        if (i >= (uint32_t)(H / 2)) { w.x = -w.x; w.y = -w.y; }
+        const C2 o = cmul(w, od);
+        const C2 F{ev.x + o.x, ev.y + o.y};
         const C2 r = cmul(F, C2{p.twist[2 * i], p.twist[2 * i + 1]});
         double xl = __builtin_rint(r.x * f), xh = __builtin_rint(r.y * f);
         if (!(__builtin_fabs(xl) < 4611686018427387904.0)) { bad = true; xl = 0.0; }
         if (!(__builtin_fabs(xh) < 4611686018427387904.0)) { bad = true; xh = 0.0; }
         mlo[c] = (long long)xl;
         mhi[c] = (long long)xh;
-    };
-    if (dense) {
+    }
+    if (bad) atomicOr(p.err, 1u);
+}
+
+// encode_split's result for a vector of at most kSparseSlots values (the
+// direct sum of encode_sparse_p0), for the encoding kernel.
+__device__ __forceinline__ void encode_sparse_split(long long (&mlo)[RS], long long (&mhi)[RS], const DevParams& p,
+                                                    const double* __restrict__ z, uint32_t n_slots, uint32_t t) {
+    const double f = 2.0 / (double)NF;
+    const uint32_t tp0 = GS::tpart(0, t);
+    bool bad = false;
 #pragma unroll
-        for (int c = 0; c < RS; ++c) {
-            const uint32_t i = jp(tp0, c);                   // < H
-            const uint32_t m1 = i & (Q - 1), m2 = (Q - m1) & (Q - 1);
-            const C2 y1 = A[padc(m1)], y2 = A[padc(m2)];
-            const C2 ev{0.5 * (y1.x + y2.x), 0.5 * (y1.y - y2.y)};     // (Y1 + conj Y2) / 2
-            const C2 od{0.5 * (y1.y + y2.y), -0.5 * (y1.x - y2.x)};    // (Y1 - conj Y2) / 2i
-            C2 w{p.fft_tw[2 * (i & (H / 2 - 1))], p.fft_tw[2 * (i & (H / 2 - 1)) + 1]};
-            if (i >= (uint32_t)(H / 2)) { w.x = -w.x; w.y = -w.y; }
-            const C2 o = cmul(w, od);
-            finish(c, i, C2{ev.x + o.x, ev.y + o.y});
-        }
-    } else {
-#pragma unroll 1
-        for (int c = 0; c < RS; ++c) {
-            const uint32_t i = jp(tp0, c);
-            finish(c, i, sparse_transform<LOGH>(p, z, n_slots, i));
-        }
+    for (int c = 0; c < RS; ++c) {
+        const uint32_t i = jp(tp0, c);                   // < N/2
+        bad |= !encode_pair(p, i, sparse_transform<14>(p, z, n_slots, i), f, mlo[c], mhi[c]);
     }
     if (bad) atomicOr(p.err, 1u);
 }

@@ -188,14 +188,14 @@ def test_encode_exact_at_moderate_magnitude(name):
         assert mism <= 2, (name, i, mism)
 
 
-SPARSE_COUNTS = (1, 2, 3, 4, 5)     # up to three values: direct sum over the slots; four, five: the transform
+SPARSE_COUNTS = (1, 2, 3, 4, 5)     # the encoding kernel: up to three values summed directly, more transformed
 
 
 @pytest.mark.parametrize("name", NAMES)
 def test_encode_sparse_slot_vectors(name):
-    """Slot vectors of at most three values skip the transform: each entry of
-    the transformed vector is summed term by term over the given slots.
-    Vectors of one to five values (up to the threshold and past it) against the
+    """The encoding kernel sums slot vectors of at most three values term by
+    term instead of transforming them.  Vectors of one to five values (up to
+    the threshold and past it) against the
     oracle's encoding under check_encoding's rules, at unit magnitude and with
     coefficients of rms about min(2^32, q_0/64), where the tie window is far
     below the rounding grid."""
@@ -221,7 +221,8 @@ def test_encode_sparse_slot_vectors(name):
 @pytest.mark.parametrize("name", NAMES)
 def test_fused_sparse_rows_against_oracle(name, scheme):
     """Fused encryption of rows of one, three and four values (Table 2's rows
-    hold 1 to 16) against the oracle's Algorithm 1 / Eq. 8 of the same slots."""
+    hold 1 to 16; the fused kernels transform every vector) against the
+    oracle's Algorithm 1 / Eq. 8 of the same slots."""
     c = gpu_ctx(name)
     P, sh, pk, zero = oracle_keys(name)
     key = zero if scheme == zinc.ZINC_SCHEME_ZINC else pk

@@ -13,7 +13,10 @@ namespace zinc {
 // ---------------------------------------------------------------------------
 // encryption
 // ---------------------------------------------------------------------------
-template <int LOGN, int SCHEME, bool FROM_SLOTS, bool BGV = false>
+// SPLIT: the workgroups y = 0 .. gridDim.y - 1 of ciphertext b share its data
+// limbs (small batches, limb_groups); otherwise one workgroup does all of them
+// (a separate instantiation, so that the usual form keeps its code).
+template <int LOGN, int SCHEME, bool FROM_SLOTS, bool BGV = false, bool SPLIT = false>
 __global__ void __launch_bounds__(Cfg<LOGN>::G::T) __attribute__((amdgpu_waves_per_eu(4)))
 k_encrypt(typename ParamArg<LOGN>::type pa, EncArgs a) {
     const DevParams& p = deref(pa);
@@ -29,7 +32,8 @@ k_encrypt(typename ParamArg<LOGN>::type pa, EncArgs a) {
     const uint32_t L = p.L;
     encrypt_item<LOGN, SCHEME, FROM_SLOTS, BGV>(p, a.slots + (size_t)b * a.n_slots, a.n_slots,
                                           a.pt + (size_t)b * L * N, id, a.ct + (size_t)b * 2 * L * N,
-                                          lds, tab, t);
+                                          lds, tab, t, SPLIT ? limb_group_start(L, blockIdx.y) : 0u,
+                                          SPLIT ? limb_group_start(L, blockIdx.y + 1) : ~0u);
 }
 
 // ---------------------------------------------------------------------------
@@ -280,8 +284,16 @@ hipError_t launch_encrypt_pt(const DevParams& p, int scheme, const uint64_t* pt,
         return launch_split_encrypt(p, scheme, false, nullptr, 0, pt, batch, ct_ids, ct, s, reserved_ok);
     EncArgs a{nullptr, 0, (const u64*)pt, (const u64*)ct_ids, (u64*)ct, reserved_ok ? 1u : 0u};
     const bool bgv = p.noise_t > 1;
-#define G_(LN, SCH, B) \
-    hipLaunchKernelGGL((k_encrypt<LN, SCH, false, B>), dim3(batch), dim3(Cfg<LN>::G::T), 0, s, ParamArg<LN>::of(p), a)
+    const uint32_t S = limb_groups(p, batch);
+#define G_(LN, SCH, B)                                                                                       \
+    do {                                                                                                     \
+        if (S > 1)                                                                                           \
+            hipLaunchKernelGGL((k_encrypt<LN, SCH, false, B, true>), dim3(batch, S), dim3(Cfg<LN>::G::T), 0, \
+                               s, ParamArg<LN>::of(p), a);                                                   \
+        else                                                                                                 \
+            hipLaunchKernelGGL((k_encrypt<LN, SCH, false, B>), dim3(batch), dim3(Cfg<LN>::G::T), 0, s,       \
+                               ParamArg<LN>::of(p), a);                                                      \
+    } while (0)
 #define F(LN)                                        \
     if (scheme == ZINC_SCHEME_ZINC) {                \
         if (bgv) G_(LN, ZINC_SCHEME_ZINC, true);     \
@@ -301,15 +313,21 @@ hipError_t launch_encrypt_slots(const DevParams& p, int scheme, const double* sl
     if (p.log_n == 15)
         return launch_split_encrypt(p, scheme, true, slots, n_slots, nullptr, batch, ct_ids, ct, s);
     EncArgs a{slots, n_slots, nullptr, (const u64*)ct_ids, (u64*)ct};
-#define F(LN)                                                                                         \
-    if (scheme == ZINC_SCHEME_ZINC)                                                                   \
-        hipLaunchKernelGGL((k_encrypt<LN, ZINC_SCHEME_ZINC, true>), dim3(batch), dim3(Cfg<LN>::G::T), \
-                           0, s, ParamArg<LN>::of(p), a);                                                               \
-    else                                                                                              \
-        hipLaunchKernelGGL((k_encrypt<LN, ZINC_SCHEME_VANILLA, true>), dim3(batch),                  \
-                           dim3(Cfg<LN>::G::T), 0, s, ParamArg<LN>::of(p), a)
+    const uint32_t S = limb_groups(p, batch);
+#define H_(LN, SCH, SP) \
+    hipLaunchKernelGGL((k_encrypt<LN, SCH, true, false, SP>), dim3(batch, S), dim3(Cfg<LN>::G::T), 0, s, \
+                       ParamArg<LN>::of(p), a)
+#define F(LN)                                                        \
+    if (scheme == ZINC_SCHEME_ZINC) {                                \
+        if (S > 1) H_(LN, ZINC_SCHEME_ZINC, true);                   \
+        else H_(LN, ZINC_SCHEME_ZINC, false);                        \
+    } else {                                                         \
+        if (S > 1) H_(LN, ZINC_SCHEME_VANILLA, true);                \
+        else H_(LN, ZINC_SCHEME_VANILLA, false);                     \
+    }
     ZINC_DISPATCH_LOGN(p.log_n, F)
 #undef F
+#undef H_
     return hipGetLastError();
 }
 

@@ -269,13 +269,19 @@ struct MessageIn {
 //
 // BGV = true (integer plaintexts only): every Gaussian error is scaled by the
 // plaintext modulus p.noise_t (Eq. 13).
+//
+// Only data limbs [l0, l1) are encrypted (all of them by default): a small
+// batch spreads each ciphertext's limbs over several workgroups, each of which
+// draws the same noise (counter-based) and encodes the same message, and
+// stashes the message in the c1 slot of its own last limb.
 template <class G, int SCHEME, bool FROM_SLOTS, bool REG_EPI = false, bool BGV = false>
 __device__ __forceinline__ void encrypt_item_g(const DevParams& p, const double* slots, uint32_t n_slots,
                                                const u64* pt, u64 ct_id, u64* ct, u64* lds, const u64* tab,
-                                               uint32_t t) {
+                                               uint32_t t, uint32_t l0 = 0, uint32_t l1 = ~0u) {
     constexpr int R = G::R, N = G::N;
     const uint32_t L = p.L;
-    long long* stash = reinterpret_cast<long long*>(ct + (size_t)(L - 1) * N);
+    if (l1 > L) l1 = L;
+    long long* stash = reinterpret_cast<long long*>(ct + (size_t)(l1 - 1) * N);
     // final ciphertext words: non-temporal from the natural-order epilogue,
     // whose wave writes whole lines; the register epilogue's strided 16-byte
     // writes measured far slower non-temporal, so they stay ordinary stores
@@ -297,7 +303,7 @@ __device__ __forceinline__ void encrypt_item_g(const DevParams& p, const double*
         sample_gauss_p0<G>(e1, p, tab, ct_id, TAG_E1Z, t);
         sample_gauss_p0<G>(e2, p, tab, ct_id, TAG_E2Z, t);
 #pragma unroll 1
-        for (uint32_t l = 0; l < L; ++l) {
+        for (uint32_t l = l0; l < l1; ++l) {
             const LimbConst lc = p.limbs[l];
             const LimbNtt<G> nt{p, lc, l, lds, t};
             const MessageIn<G, FROM_SLOTS, BGV> msg{stash, pt + (size_t)l * N, e1.fresh(), lc,
@@ -328,7 +334,7 @@ __device__ __forceinline__ void encrypt_item_g(const DevParams& p, const double*
         sample_gauss_p0<G>(e2, p, tab, ct_id, TAG_E2, t);
         const uint32_t M = p.M;
 #pragma unroll 1
-        for (uint32_t l = 0; l < L; ++l) {
+        for (uint32_t l = l0; l < l1; ++l) {
             const LimbConst lc = p.limbs[l];
             const LimbNtt<G> nt{p, lc, l, lds, t};
             u64* c1 = ct + (size_t)l * N;
@@ -369,9 +375,12 @@ __device__ __forceinline__ void encrypt_item_g(const DevParams& p, const double*
 template <int LOGN, int SCHEME, bool FROM_SLOTS, bool BGV = false>
 __device__ __forceinline__ void encrypt_item(const DevParams& p, const double* slots, uint32_t n_slots,
                                              const u64* pt, u64 ct_id, u64* ct, u64* lds, const u64* tab,
-                                             uint32_t t) {
+                                             uint32_t t, uint32_t l0 = 0, uint32_t l1 = ~0u) {
     encrypt_item_g<typename Cfg<LOGN>::G, SCHEME, FROM_SLOTS, false, BGV>(p, slots, n_slots, pt, ct_id, ct, lds,
-                                                                          tab, t);
+                                                                          tab, t, l0, l1);
 }
+
+// Data limbs of workgroup y of gridDim.y that share one ciphertext.
+__device__ __forceinline__ uint32_t limb_group_start(uint32_t L, uint32_t y) { return y * L / gridDim.y; }
 
 }  // namespace zinc

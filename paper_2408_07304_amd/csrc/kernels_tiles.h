@@ -13,7 +13,8 @@ namespace {  // each including translation unit has its own copy
 
 // WPE: waves per SIMD that the register budget must allow (the LDS buffer of
 // one ciphertext already bounds the workgroups per CU).
-template <class G, int SCHEME, int WPE, bool REG>
+// SPLIT: as for k_encrypt, the workgroups along y share a ciphertext's limbs.
+template <class G, int SCHEME, int WPE, bool REG, bool SPLIT>
 __global__ void __launch_bounds__(G::T) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_encrypt_tile(typename ParamArg<G::LOGN>::type pa, EncArgs a) {
     const DevParams& p = deref(pa);
@@ -26,12 +27,20 @@ k_encrypt_tile(typename ParamArg<G::LOGN>::type pa, EncArgs a) {
     if (reserved_id(p, a, id, t)) return;
     load_cdt(tab, p.cdt, t);
     encrypt_item_g<G, SCHEME, true, REG>(p, a.slots + (size_t)b * a.n_slots, a.n_slots, nullptr, id,
-                                    a.ct + (size_t)b * 2 * p.L * N, lds, tab, t);
+                                         a.ct + (size_t)b * 2 * p.L * N, lds, tab, t,
+                                         SPLIT ? limb_group_start(p.L, blockIdx.y) : 0u,
+                                         SPLIT ? limb_group_start(p.L, blockIdx.y + 1) : ~0u);
 }
 
 template <class G, int SCHEME, int WPE, bool REG>
 hipError_t launch_tile(const DevParams& p, const EncArgs& a, uint32_t batch, hipStream_t s) {
-    hipLaunchKernelGGL((k_encrypt_tile<G, SCHEME, WPE, REG>), dim3(batch), dim3(G::T), 0, s, ParamArg<G::LOGN>::of(p), a);
+    const uint32_t S = limb_groups(p, batch);
+    if (S > 1)
+        hipLaunchKernelGGL((k_encrypt_tile<G, SCHEME, WPE, REG, true>), dim3(batch, S), dim3(G::T), 0, s,
+                           ParamArg<G::LOGN>::of(p), a);
+    else
+        hipLaunchKernelGGL((k_encrypt_tile<G, SCHEME, WPE, REG, false>), dim3(batch), dim3(G::T), 0, s,
+                           ParamArg<G::LOGN>::of(p), a);
     return hipGetLastError();
 }
 

@@ -45,6 +45,12 @@ int device_cu_count() {
     return cus > 0 ? cus : 256;
 }
 
+uint32_t limb_groups(const DevParams& p, uint32_t batch) {
+    static const uint32_t cus = (uint32_t)device_cu_count();
+    if (batch == 0 || 2 * batch > cus) return 1;
+    return std::max(1u, std::min(p.L, cus / batch));
+}
+
 double plan_unit_cost(const zinc_ctx& c, const PlanUnit& u) {
     return (double)u.count * c.n * c.log_n * ((double)(u.l1 - u.l0) + 1.0);
 }

@@ -179,6 +179,11 @@ void set_error(const std::string& msg);
 hipError_t launch_keygen(const DevParams& p, uint64_t* sk, uint64_t* sk_sh, uint64_t* pk,
                          uint64_t* pk_sh, hipStream_t s);
 // reserved_ok: the identifiers may be reserved ones (the cached Enc(0) only)
+// Workgroups per ciphertext of the fused kernels for N <= 16384: a batch of
+// fewer than half as many ciphertexts as the device has CUs leaves CUs idle
+// with one workgroup per ciphertext, so each ciphertext's data limbs are
+// spread over up to CUs / batch workgroups (at most one limb each).
+uint32_t limb_groups(const DevParams& p, uint32_t batch);
 hipError_t launch_encrypt_pt(const DevParams& p, int scheme, const uint64_t* pt, uint32_t batch,
                              const uint64_t* ct_ids, uint64_t* ct, hipStream_t s, bool reserved_ok = false);
 hipError_t launch_encrypt_slots(const DevParams& p, int scheme, const double* slots,

@@ -238,6 +238,39 @@ def test_fused_sparse_rows_against_oracle(name, scheme):
             check_fused(c, P, scheme, key, z[i], cid[i], got[i], (name, scheme, n, i))
 
 
+@pytest.mark.parametrize("name", ["n4096", "n8192", "n16384"])
+def test_small_batch_limb_split_equals_full_launch(name):
+    """A batch of fewer ciphertexts than half the device's CUs spreads each
+    ciphertext's data limbs over several workgroups (each draws the same noise
+    and encodes the same message); its ciphertexts equal those of a batch large
+    enough to take one workgroup per ciphertext, from slots and from
+    plaintexts, for both schemes, and the first one equals the oracle's."""
+    c = gpu_ctx(name)
+    P, sh, pk, zero = oracle_keys(name)
+    rng = np.random.default_rng(37)
+    big_b = 300
+    z = rng.uniform(-1, 1, size=(big_b, P.n // 2))
+    pt = _plaintexts(P, 4, 43)
+    for scheme in SCHEMES:
+        key = zero if scheme == zinc.ZINC_SCHEME_ZINC else pk
+        big = empty_u64(big_b, 2, P.L, P.n)
+        small = empty_u64(3, 2, P.L, P.n)
+        say(f"{name} scheme={scheme}: {big_b} slot vectors in one launch, then 3 alone")
+        c.encrypt_slots(scheme, to_dev(z), ids(range(big_b)), big)
+        c.encrypt_slots(scheme, to_dev(z[:3]), ids(range(3)), small)
+        got_big, got_small = from_dev(big), from_dev(small)
+        assert np.array_equal(got_big[:3], got_small), (name, scheme)
+        check_fused(c, P, scheme, key, z[0], 0, got_small[0], (name, scheme, "split"))
+        # plaintext path: 4 alone (split) against the same 4 inside a batch of big_b
+        pts = np.concatenate([pt, np.repeat(pt[:1], big_b - 4, axis=0)])
+        enc = c.encrypt if scheme == zinc.ZINC_SCHEME_ZINC else c.encrypt_vanilla
+        outb = empty_u64(big_b, 2, P.L, P.n)
+        outs = empty_u64(4, 2, P.L, P.n)
+        enc(to_dev(pts), ids(range(100, 100 + big_b)), outb)
+        enc(to_dev(pt), ids(range(100, 104)), outs)
+        assert np.array_equal(from_dev(outb)[:4], from_dev(outs)), (name, scheme, "pt")
+
+
 @pytest.mark.parametrize("scheme", SCHEMES)
 @pytest.mark.parametrize("name", NAMES)
 def test_fused_equals_encode_then_encrypt(name, scheme):

@@ -3,7 +3,9 @@
 // graph and replayed.
 #include <algorithm>
 #include <cstring>
+#include <functional>
 #include <new>
+#include <queue>
 #include <string>
 #include <vector>
 
@@ -55,6 +57,41 @@ double plan_unit_cost(const zinc_ctx& c, const PlanUnit& u) {
     return (double)u.count * c.n * c.log_n * ((double)(u.l1 - u.l0) + 1.0);
 }
 
+// Completion time of units of the given costs on `round` workgroups that
+// each take the next unit, longest first, when they become free (how k_plan
+// runs a plan).
+static double list_makespan(std::vector<double> costs, uint32_t round) {
+    std::sort(costs.begin(), costs.end(), std::greater<double>());
+    std::priority_queue<double, std::vector<double>, std::greater<double>> free_at;
+    for (uint32_t i = 0; i < std::max(round, 1u); ++i) free_at.push(0.0);
+    double end = 0.0;
+    for (double c : costs) {
+        const double t = free_at.top() + c;
+        free_at.pop();
+        free_at.push(t);
+        end = std::max(end, t);
+    }
+    return end;
+}
+
+uint32_t plan_split_parts(const std::vector<double>& other_costs, uint32_t tail, uint32_t L, double unit,
+                          uint32_t round) {
+    uint32_t best = std::min(kPlanSplit, L);
+    double best_end = 1e300;
+    for (uint32_t parts = best; parts <= L; ++parts) {
+        std::vector<double> costs = other_costs;
+        for (uint32_t i = 0; i < tail; ++i)
+            for (uint32_t j = 0; j < parts; ++j)
+                costs.push_back(unit * ((double)((j + 1) * L / parts - j * L / parts) + 1.0));
+        const double end = list_makespan(std::move(costs), round);
+        if (end < best_end * (1.0 - 1e-9)) {
+            best_end = end;
+            best = parts;
+        }
+    }
+    return best;
+}
+
 uint64_t build_plan_tables(zinc_ctx* const* ctxs, uint32_t n_ctx, const zinc_item* items, uint32_t n_items,
                            std::vector<PlanItem>& dev_items, std::vector<PlanUnit>& units, uint32_t round) {
     dev_items.clear();
@@ -66,11 +103,44 @@ uint64_t build_plan_tables(zinc_ctx* const* ctxs, uint32_t n_ctx, const zinc_ite
     // last whole round of `round` units would run in a partial round of their
     // own while the other workgroups idle; split into limb groups, they spread
     // over all workgroups (each group redraws the same noise and re-encodes
-    // the message, about one limb's work).
+    // the message, about one limb's work).  The number of groups minimises the
+    // estimated completion time of the plan (plan_split_parts): a few such
+    // ciphertexts on an idle device take one limb per unit, a full device
+    // keeps kPlanSplit.
     uint32_t n32 = 0;
     for (uint32_t c = 0; c < n_ctx; ++c)
         if (ctxs[c]->log_n == 15) n32 += (uint32_t)per_ctx[c].size();
     const uint32_t tail = round ? n32 % round : 0;
+    // estimated costs of every unit but the tail's, and the tail per context
+    std::vector<double> other_costs;
+    std::vector<uint32_t> tail_of(n_ctx, 0);
+    {
+        uint32_t seen = 0;
+        for (uint32_t c = 0; c < n_ctx; ++c) {
+            const zinc_ctx* cx = ctxs[c];
+            const uint32_t g = plan_units_per_group(cx->log_n);
+            const double whole = plan_unit_cost(*cx, PlanUnit{c, cx->log_n, 0u, g, 0u, cx->L});
+            for (size_t k = 0; k < per_ctx[c].size(); k += g) {
+                if (cx->log_n == 15 && seen++ >= n32 - tail) ++tail_of[c];
+                else other_costs.push_back(whole);
+            }
+        }
+    }
+    std::vector<uint32_t> parts_of(n_ctx, 1);
+    for (uint32_t c = 0; c < n_ctx; ++c) {
+        if (!tail_of[c]) continue;
+        std::vector<double> others = other_costs;   // the other contexts' tails at the fewest groups
+        for (uint32_t d = 0; d < n_ctx; ++d) {
+            if (d == c || !tail_of[d]) continue;
+            const uint32_t pd = std::min(kPlanSplit, ctxs[d]->L);
+            for (uint32_t i = 0; i < tail_of[d]; ++i)
+                for (uint32_t j = 0; j < pd; ++j)
+                    others.push_back(plan_unit_cost(*ctxs[d], PlanUnit{d, 15u, 0u, 1u, j * ctxs[d]->L / pd,
+                                                                       (j + 1) * ctxs[d]->L / pd}));
+        }
+        parts_of[c] = plan_split_parts(others, tail_of[c], ctxs[c]->L,
+                                       plan_unit_cost(*ctxs[c], PlanUnit{c, 15u, 0u, 1u, 0u, 0u}), round);
+    }
     uint32_t seen32 = 0;
     for (uint32_t c = 0; c < n_ctx; ++c) {
         const zinc_ctx* cx = ctxs[c];
@@ -79,7 +149,7 @@ uint64_t build_plan_tables(zinc_ctx* const* ctxs, uint32_t n_ctx, const zinc_ite
         const auto& lst = per_ctx[c];
         for (size_t s = 0; s < lst.size(); s += g) {
             if (cx->log_n == 15 && seen32++ >= n32 - tail) {
-                const uint32_t parts = std::min(kPlanSplit, cx->L);
+                const uint32_t parts = parts_of[c];
                 for (uint32_t j = 0; j < parts; ++j)
                     units.push_back(PlanUnit{c, cx->log_n, (uint32_t)dev_items.size(), 1u, j * cx->L / parts,
                                              (j + 1) * cx->L / parts});

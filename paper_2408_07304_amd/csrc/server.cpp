@@ -243,9 +243,12 @@ zinc_status zinc_server_create(zinc_ctx* const* ctxs, uint32_t n_ctx, const zinc
     s->arena = Arena(budget);
     s->cus = device_cu_count();
     // Per-batch table capacity: every plaintext plus the padding of one
-    // partial unit per context; a plaintext is at most kPlanSplit units.
+    // partial unit per context; a plaintext is at most max(kPlanSplit, L) units.
     s->item_cap = cfg->max_batch + 3ull * n_ctx;
-    s->unit_cap = (size_t)kPlanSplit * cfg->max_batch + (size_t)n_ctx;
+    uint32_t max_split = kPlanSplit;            // a plaintext of ring degree 32768 is at most L units
+    for (uint32_t c = 0; c < n_ctx; ++c)
+        if (ctxs[c]->log_n == 15) max_split = std::max(max_split, ctxs[c]->L);
+    s->unit_cap = (size_t)max_split * cfg->max_batch + (size_t)n_ctx;
     const uint64_t dummy_words = std::max<uint64_t>(1, plan_dummy_words(ctxs, n_ctx));
     auto al = [](size_t x) { return (x + kAlign - 1) & ~size_t(kAlign - 1); };
     const size_t b_ctx = al(sizeof(DevParams) * n_ctx), b_items = al(sizeof(PlanItem) * s->item_cap);

@@ -254,8 +254,16 @@ uint64_t build_plan_tables(zinc_ctx* const* ctxs, uint32_t n_ctx, const zinc_ite
                            std::vector<PlanItem>& dev_items, std::vector<PlanUnit>& units, uint32_t round);
 // Estimated cost of a unit (relative): per item, N log N times the unit's
 // limbs plus one limb's worth for the encoding and sampling every unit does.
+// Limb groups of each of the `tail` ring-degree-32768 ciphertexts of a last
+// partial round of a plan: the count in [kPlanSplit, L] that minimises the
+// plan's completion time on `round` workgroups that take units longest first
+// (costs as plan_unit_cost: `unit` is one limb's cost, a group of g limbs costs
+// unit * (g + 1); `other_costs` are the plan's other units); ties go to fewer
+// groups.
+uint32_t plan_split_parts(const std::vector<double>& other_costs, uint32_t tail, uint32_t L, double unit,
+                          uint32_t round);
 double plan_unit_cost(const zinc_ctx& c, const PlanUnit& u);
-constexpr uint32_t kPlanSplit = 4;        // limb groups of a split ring-degree-32768 ciphertext
+constexpr uint32_t kPlanSplit = 4;        // fewest limb groups of a split ring-degree-32768 ciphertext
 uint64_t plan_dummy_words(zinc_ctx* const* ctxs, uint32_t n_ctx);
 int device_cu_count();
 zinc_status plan_fail(zinc_status code, const std::string& msg);

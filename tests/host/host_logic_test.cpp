@@ -102,10 +102,38 @@ static int test_plan_tables() {
         }
         CHECK(!di[u.first].dummy);                       // a unit starts with a real item
     }
-    // the ciphertexts beyond the last whole round of 16 are split in four
+    // the ciphertexts beyond the last whole round of 16 are split, here (many
+    // units of work per workgroup) into the fewest groups
     CHECK(split_units == (n32 % round) * zinc::kPlanSplit);
     CHECK(limbs_done.size() == items.size());
     for (const zinc_item& it : items) CHECK(limbs_done[it.ct_id] == (1u << ctx[it.ctx_idx].L) - 1u);
+
+    // a light batch (a few ciphertexts, idle workgroups): one limb per unit
+    std::vector<zinc_item> few;
+    for (uint32_t i = 0; i < 3; ++i) few.push_back(zinc_item{2u, 0u, 1000ull * i, 7000ull * i, 900ull + i});
+    few.push_back(zinc_item{1u, 0u, 5000ull, 9000ull, 990ull});
+    zinc::build_plan_tables(cp.data(), 4, few.data(), (uint32_t)few.size(), di, un, 256);
+    uint32_t n_split = 0;
+    std::map<uint64_t, uint32_t> covered;
+    for (const zinc::PlanUnit& u : un) {
+        if (ctx[u.ctx].log_n == 15) {
+            CHECK(u.l1 - u.l0 == 1u);
+            ++n_split;
+        }
+        for (uint32_t l = u.l0; l < u.l1; ++l) covered[di[u.first].ct_id] |= 1u << l;
+    }
+    CHECK(n_split == 3u * ctx[2].L);
+    for (const zinc_item& it : few) CHECK(covered[it.ct_id] == (1u << ctx[it.ctx_idx].L) - 1u);
+
+    // the rule itself: a lone ciphertext on an idle device takes one limb per
+    // unit; 64 on 256 workgroups keep four groups (256 units, one round: five
+    // groups would need a second round); a long queue keeps the fewest
+    const std::vector<double> none;
+    CHECK(zinc::plan_split_parts(none, 1, 14, 1.0, 256) == 14u);
+    CHECK(zinc::plan_split_parts(none, 64, 14, 1.0, 256) == zinc::kPlanSplit);
+    CHECK(zinc::plan_split_parts(none, 16, 14, 1.0, 256) == 14u);
+    CHECK(zinc::plan_split_parts(std::vector<double>(4000, 15.0), 100, 14, 1.0, 16) == zinc::kPlanSplit);
+    CHECK(zinc::plan_split_parts(none, 1, 3, 1.0, 256) == 3u);   // never more groups than limbs
     return 0;
 }
 

@@ -295,6 +295,10 @@ __device__ __forceinline__ void lds_get(const T* lds, T (&v)[G::R], uint32_t t) 
 // after them.
 template <class G, int P1, int P2, class T>
 __device__ __forceinline__ void exchange(T* lds, T (&v)[G::R], uint32_t t) {
+    // A forward transform's first exchange follows LDS use of the caller (often
+    // reads in natural order, across waves): it must take barriers.  With
+    // K(0) + K(1) above log R it always does.
+    static_assert(!(P1 == 0 && P2 == 1) || !wave_local<G>(0, 1), "first exchange must take barriers");
     if constexpr (wave_local<G>(P1, P2)) {
         wave_lds_fence();
         lds_put<G, P1>(lds, v, t);
@@ -457,12 +461,19 @@ __device__ __forceinline__ void ntt_inv(u64 (&v)[G::R], u64* lds, const u64* __r
     inv_rest<G, PL - 1>(v, lds, itw, toff, smul, q, q2, t);
 }
 
-// Write v (last forward pass layout) to LDS so that lds[pad(i)] is coefficient i
-// (across waves: workgroup barriers).
+// Write v (last forward pass layout) to LDS so that lds[pad(i)] is coefficient i,
+// then a workgroup barrier: readers of the natural order span all waves.  Called
+// straight after ntt_fwd / ntt_fwd_fp, whose last LDS accesses were each wave's
+// reads of its own indices of the last pass -- the very words it now writes --
+// while the other waves can still be reading only their own, disjoint, words.
+// So no barrier is needed before the writes, only a compiler barrier that keeps
+// them after those reads (a single-pass transform has no exchange and keeps the
+// barrier).
 template <class G, class T>
 __device__ __forceinline__ void to_natural(T* lds, const T (&v)[G::R], uint32_t t_) {
     const uint32_t t = opaque_tid(t_);
-    __syncthreads();
+    if constexpr (G::NPASS > 1) wave_lds_fence();
+    else __syncthreads();
     lds_put<G, G::NPASS - 1>(lds, v, t);
     __syncthreads();
 }

@@ -478,6 +478,32 @@ __device__ __forceinline__ void to_natural(T* lds, const T (&v)[G::R], uint32_t 
     __syncthreads();
 }
 
+// The same writes with no barrier after them, for readers that take only their
+// own wave's words (wave_pair_index): in the last pass a wave holds whole blocks
+// of 64 * 2^K consecutive coefficients.  A later writer of other words must
+// still take a workgroup barrier first, as a forward transform's first
+// exchange and the encoder do.
+template <class G, class T>
+__device__ __forceinline__ void to_natural_wave(T* lds, const T (&v)[G::R], uint32_t t_) {
+    static_assert(G::NPASS > 1, "follows the transform's last exchange");
+    const uint32_t t = opaque_tid(t_);
+    wave_lds_fence();
+    lds_put<G, G::NPASS - 1>(lds, v, t);
+    wave_lds_fence();
+}
+
+// Coefficient index of the i-th pair (i < R/2) that thread t takes after
+// to_natural_wave: the pairs of each of its wave's blocks go to consecutive
+// lanes, so each read, load and store of a pair by the wave covers 128
+// consecutive coefficients.
+template <class G>
+__device__ __forceinline__ uint32_t wave_pair_index(uint32_t t, int i) {
+    constexpr int PL = G::NPASS - 1, K = G::K(PL);
+    static_assert(G::LO(PL) == 0 && K >= 1 && G::LOGT >= 6, "last pass covers bit 0");
+    const uint32_t h = (uint32_t)i >> (K - 1), j = (uint32_t)i & ((1u << (K - 1)) - 1u);
+    return (h << (G::LOGT + K)) | ((t >> 6) << (6 + K)) | (j << 7) | ((t & 63u) << 1);
+}
+
 // ---- FP64 path (moduli below 2^50): exact integer arithmetic in doubles ----
 //
 // MI355X issues FP64 FMA at the full VALU rate, so for moduli below 2^50 the

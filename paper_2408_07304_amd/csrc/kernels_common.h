@@ -77,8 +77,10 @@ struct LimbNtt {
     // Transform the pass-0 inputs given by in(c) (integer path: a residue in
     // [0, 2q); FP path: an exact integer of magnitude at most q, as double).
     // hook() runs after the last pass, before the exchange into natural
-    // order (early loads of epilogue operands go there).
-    template <class InInt, class InFp, class Hook>
+    // order (early loads of epilogue operands go there).  WAVE: each wave then
+    // reads back only its own blocks (wave_pair_index), with no workgroup
+    // barrier; else any thread may read any coefficient.
+    template <bool WAVE = false, class InInt, class InFp, class Hook>
     __device__ __forceinline__ void run(InInt in_int, InFp in_fp, Hook hook) const {
         if (fp()) {
             double v[G::R];
@@ -87,14 +89,16 @@ struct LimbNtt {
             double* ld = reinterpret_cast<double*>(lds);
             ntt_fwd_fp<G>(v, ld, tw_fp, limb, qd, qinv, mode == 2, t);
             hook();
-            to_natural<G>(ld, v, t);
+            if constexpr (WAVE) to_natural_wave<G>(ld, v, t);
+            else to_natural<G>(ld, v, t);
         } else {
             u64 v[G::R];
 #pragma unroll
             for (int c = 0; c < G::R; ++c) v[c] = in_int(c);
             ntt_fwd<G>(v, lds, tw, limb, q, q2, t);
             hook();
-            to_natural<G>(lds, v, t);
+            if constexpr (WAVE) to_natural_wave<G>(lds, v, t);
+            else to_natural<G>(lds, v, t);
         }
     }
     template <class InInt, class InFp>
@@ -164,9 +168,10 @@ __device__ __forceinline__ void store_pair_final(u64* p, u64 a, u64 b) {
 // Transform one polynomial of a limb and hand every coefficient pair the
 // thread owns to epi(k, v_k, v_k+1, pre(k)) (k even, canonical values; pre(k)
 // an operand of the epilogue loaded for that pair).  REG = false: back to
-// natural order through LDS, so that each store instruction of a workgroup's
-// waves covers one contiguous span; pre(k) is issued after the last pass, so
-// its latency overlaps that exchange.  REG = true: straight from the
+// natural order through LDS within each wave, so that each store instruction
+// of a wave covers 128 consecutive coefficients; pre(k) is issued after the
+// last pass, so its latency overlaps that exchange.  A thread takes the same
+// pairs in every transform of a given geometry.  REG = true: straight from the
 // registers of the last pass, whose runs of consecutive coefficients give
 // 2^K-strided accesses but no LDS round trip.  Which is faster depends on the
 // ring degree and the scheme (autotuned).
@@ -184,15 +189,15 @@ __device__ __forceinline__ void transform_store_pre(const LimbNtt<G>& nt, uint32
         }
     } else {
         decltype(pre(0u)) pv[G::R / 2];
-        nt.run(in_int, in_fp, [&]() {
+        nt.template run<true>(in_int, in_fp, [&]() {
             const uint32_t tt = opaque_tid(t);
 #pragma unroll
-            for (int i = 0; i < G::R / 2; ++i) pv[i] = pre(2 * (tt + G::T * i));
+            for (int i = 0; i < G::R / 2; ++i) pv[i] = pre(wave_pair_index<G>(tt, i));
         });
         const uint32_t tt = opaque_tid(t);
 #pragma unroll
         for (int i = 0; i < G::R / 2; ++i) {
-            const uint32_t k = 2 * (tt + G::T * i);
+            const uint32_t k = wave_pair_index<G>(tt, i);
             epi(k, nt.canon(k), nt.canon(k + 1), pv[i]);
         }
     }

@@ -155,8 +155,9 @@ struct SplitLimb {
     }
 
     // half-h transform of the pass-0 values in(c) (raw patterns); leaves the
-    // result in LDS in natural order of the half
-    template <class In>
+    // result in LDS in natural order of the half.  WAVE: each wave then reads
+    // back only its own blocks (wave_pair_index), with no workgroup barrier.
+    template <bool WAVE = false, class In>
     __device__ __forceinline__ void run_half(int h, In in) const {
         if (fp()) {
             double v[RS];
@@ -164,13 +165,15 @@ struct SplitLimb {
             for (int c = 0; c < RS; ++c) v[c] = __longlong_as_double((long long)in(c));
             double* ld = reinterpret_cast<double*>(lds);
             ntt_fwd_fp<GS>(v, ld, tw_fp, limb, qd, qinv, mode == 2, t, 2u + (uint32_t)h, NF);
-            to_natural<GS>(ld, v, t);
+            if constexpr (WAVE) to_natural_wave<GS>(ld, v, t);
+            else to_natural<GS>(ld, v, t);
         } else {
             u64 v[RS];
 #pragma unroll
             for (int c = 0; c < RS; ++c) v[c] = in(c);
             ntt_fwd<GS>(v, lds, tw, limb, q, q2, t, 2u + (uint32_t)h, NF);
-            to_natural<GS>(lds, v, t);
+            if constexpr (WAVE) to_natural_wave<GS>(lds, v, t);
+            else to_natural<GS>(lds, v, t);
         }
     }
 
@@ -289,7 +292,16 @@ __device__ __forceinline__ void encrypt_item_split(const DevParams& p, const dou
 
     // message transform of limb l into dst (natural order) with epilogue
     // epi(k, value_k, value_k+1) on pairs (k even: one 16-byte access; a wave
-    // covers whole lines)
+    // covers whole lines).  Vanilla's epilogues take each wave's own blocks of
+    // the last pass (wave_pair_index, no barrier after the write-back: 2 %
+    // faster); Zinc's, which load the cached Enc(0) in the epilogue, measured
+    // 1 % slower that way (each moment's accesses of the workgroup are spread
+    // over 4 KiB blocks), so they take consecutive pairs across the waves.
+    constexpr bool WAVE = SCHEME != ZINC_SCHEME_ZINC;
+    auto pair_index = [](uint32_t tt, int i) -> uint32_t {
+        if constexpr (WAVE) return wave_pair_index<GS>(tt, i);
+        else return 2 * (tt + TS * i);
+    };
     auto message_ntt = [&](const SplitLimb& sl, const LimbConst& lc, uint32_t l, const Packed8<RS>& elo,
                            const Packed8<RS>& ehi, u64* dst, auto&& epi) {
         const uint32_t tp0 = GS::tpart(0, opaque_tid(t));
@@ -309,22 +321,22 @@ __device__ __forceinline__ void encrypt_item_split(const DevParams& p, const dou
             u[c] = sl.stage0(xl, xh, 0);
             dst[NH + k] = sl.stage0(xl, xh, 1);          // half-1 input, read back below
         }
-        sl.run_half(0, [&](int c) { return u[c]; });
+        sl.template run_half<WAVE>(0, [&](int c) { return u[c]; });
         {
             const uint32_t tt = opaque_tid(t);
 #pragma unroll
             for (int i = 0; i < RS / 2; ++i) {
-                const uint32_t k = 2 * (tt + TS * i);
+                const uint32_t k = pair_index(tt, i);
                 epi(k, sl.canon(k), sl.canon(k + 1));
             }
         }
         const uint32_t tp1 = GS::tpart(0, opaque_tid(t));
-        sl.run_half(1, [&](int c) { return dst[NH + jp(tp1, c)]; });
+        sl.template run_half<WAVE>(1, [&](int c) { return dst[NH + jp(tp1, c)]; });
         {
             const uint32_t tt = opaque_tid(t);
 #pragma unroll
             for (int i = 0; i < RS / 2; ++i) {
-                const uint32_t k = 2 * (tt + TS * i);
+                const uint32_t k = pair_index(tt, i);
                 epi(NH + k, sl.canon(k), sl.canon(k + 1));
             }
         }
@@ -336,13 +348,13 @@ __device__ __forceinline__ void encrypt_item_split(const DevParams& p, const dou
 #pragma unroll 1
         for (int h = 0; h < 2; ++h) {
             const Pair8 el = e.fresh();
-            sl.run_half(h, [&](int c) {
+            sl.template run_half<WAVE>(h, [&](int c) {
                 return sl.stage0(sl.noise<S>(el.lo.get(c), p.noise_t, lc), sl.noise<S>(el.hi.get(c), p.noise_t, lc), h);
             });
             const uint32_t tt = opaque_tid(t);
 #pragma unroll
             for (int i = 0; i < RS / 2; ++i) {
-                const uint32_t k = 2 * (tt + TS * i);
+                const uint32_t k = pair_index(tt, i);
                 epi((uint32_t)h * NH + k, sl.canon(k), sl.canon(k + 1));
             }
         }

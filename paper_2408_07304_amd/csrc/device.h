@@ -497,7 +497,7 @@ __device__ __forceinline__ void to_natural_wave(T* lds, const T (&v)[G::R], uint
 // lanes, so each read, load and store of a pair by the wave covers 128
 // consecutive coefficients.
 template <class G>
-__device__ __forceinline__ uint32_t wave_pair_index(uint32_t t, int i) {
+__host__ __device__ __forceinline__ uint32_t wave_pair_index(uint32_t t, int i) {
     constexpr int PL = G::NPASS - 1, K = G::K(PL);
     static_assert(G::LO(PL) == 0 && K >= 1 && G::LOGT >= 6, "last pass covers bit 0");
     const uint32_t h = (uint32_t)i >> (K - 1), j = (uint32_t)i & ((1u << (K - 1)) - 1u);
@@ -712,7 +712,8 @@ __device__ __forceinline__ void fft_dit(C2* A, const double* __restrict__ fft_tw
 // (B = p LOGR, K = min(LOGR, LOGH - B)) come from a thread's register number
 // and the other bits from its thread index (then its remaining register bits):
 // every thread loads its 2^LOGR points, applies the pass's stages and stores
-// them back to the same places, so one barrier per pass suffices.  Every
+// them back to the same places, so one barrier per pass suffices (none between
+// passes that keep each wave on its own words, see fft_wave_local).  Every
 // butterfly performs the operations of fft_dit on the same values, so the
 // result equals fft_dit's bit for bit, for any T.  A is indexed through padc().
 // PARTIAL: the workgroup has more than T threads; all of them reach the
@@ -725,11 +726,25 @@ template <int LOGH, int LOGT, int P>
 struct FftPass {
     static constexpr int LOGR = LOGH - LOGT, R = 1 << LOGR;
     static constexpr int B = P * LOGR, K = (LOGH - B < LOGR) ? LOGH - B : LOGR;
-    __device__ static __forceinline__ uint32_t idx(uint32_t t, int e) {
+    __host__ __device__ static __forceinline__ uint32_t idx(uint32_t t, int e) {
         const uint32_t c = (uint32_t)e & ((1u << K) - 1u), rest = t | ((uint32_t)(e >> K) << LOGT);
         return (rest & ((1u << B) - 1u)) | (c << B) | ((rest >> B) << (B + K));
     }
 };
+
+// Passes P and P + 1 touch the same words in each wavefront when every wave bit
+// of the thread index (those above its 64 lanes) sits on the same index bit in
+// both: a thread bit b lands on bit b below a pass's base B, else on b + K.
+// Between such passes a wave reads back only its own stores, which the LDS
+// executes in order, so no workgroup barrier is needed (as for wave_local).
+template <int LOGH, int LOGT, int P>
+__host__ __device__ constexpr bool fft_wave_local() {
+    using F0 = FftPass<LOGH, LOGT, P>;
+    using F1 = FftPass<LOGH, LOGT, P + 1>;
+    for (int b = 6; b < LOGT; ++b)
+        if ((b < F0::B ? b : b + F0::K) != (b < F1::B ? b : b + F1::K)) return false;
+    return true;
+}
 
 // The twiddles of pass P, w[k][e] for stage k and the registers e that start
 // a butterfly; they depend on the thread index only, so they are requested
@@ -786,7 +801,9 @@ __device__ __forceinline__ void fft_reg_pass(C2* A, const double* __restrict__ f
         FftTw<LOGH, LOGT, SIGN, LOGTAB, P + 1> next;
         if constexpr (F::B + F::LOGR < LOGH)
             if (active) next = fft_pass_tw<LOGH, LOGT, SIGN, LOGTAB, P + 1>(fft_tw, t);
-        __syncthreads();
+        // the last pass's stores are read by every thread: a barrier
+        if constexpr (F::B + F::LOGR < LOGH && fft_wave_local<LOGH, LOGT, P>()) wave_lds_fence();
+        else __syncthreads();
         fft_reg_pass<LOGH, LOGT, SIGN, LOGTAB, P + 1, PARTIAL>(A, fft_tw, t, next);
     }
 }

@@ -157,14 +157,17 @@ struct SplitLimb {
     // half-h transform of the pass-0 values in(c) (raw patterns); leaves the
     // result in LDS in natural order of the half.  WAVE: each wave then reads
     // back only its own blocks (wave_pair_index), with no workgroup barrier.
-    template <bool WAVE = false, class In>
-    __device__ __forceinline__ void run_half(int h, In in) const {
+    // hook() runs after the last pass, before the write-back (early loads of
+    // epilogue operands go there).
+    template <bool WAVE = false, class In, class Hook>
+    __device__ __forceinline__ void run_half(int h, In in, Hook hook) const {
         if (fp()) {
             double v[RS];
 #pragma unroll
             for (int c = 0; c < RS; ++c) v[c] = __longlong_as_double((long long)in(c));
             double* ld = reinterpret_cast<double*>(lds);
             ntt_fwd_fp<GS>(v, ld, tw_fp, limb, qd, qinv, mode == 2, t, 2u + (uint32_t)h, NF);
+            hook();
             if constexpr (WAVE) to_natural_wave<GS>(ld, v, t);
             else to_natural<GS>(ld, v, t);
         } else {
@@ -172,9 +175,14 @@ struct SplitLimb {
 #pragma unroll
             for (int c = 0; c < RS; ++c) v[c] = in(c);
             ntt_fwd<GS>(v, lds, tw, limb, q, q2, t, 2u + (uint32_t)h, NF);
+            hook();
             if constexpr (WAVE) to_natural_wave<GS>(lds, v, t);
             else to_natural<GS>(lds, v, t);
         }
+    }
+    template <bool WAVE = false, class In>
+    __device__ __forceinline__ void run_half(int h, In in) const {
+        run_half<WAVE>(h, in, []() {});
     }
 
     __device__ __forceinline__ u64 canon(uint32_t k) const {
@@ -291,8 +299,10 @@ __device__ __forceinline__ void encrypt_item_split(const DevParams& p, const dou
     }
 
     // message transform of limb l into dst (natural order) with epilogue
-    // epi(k, value_k, value_k+1) on pairs (k even: one 16-byte access; a wave
-    // covers whole lines).  Vanilla's epilogues take each wave's own blocks of
+    // epi(k, value_k, value_k+1, pre(k)) on pairs (k even: one 16-byte access;
+    // a wave covers whole lines); pre(k), an operand of the epilogue, is loaded
+    // after the last pass so that its latency overlaps the write-back (one
+    // workgroup per CU: no other workgroup hides it).  Vanilla's epilogues take each wave's own blocks of
     // the last pass (wave_pair_index, no barrier after the write-back: 2 %
     // faster); Zinc's, which load the cached Enc(0) in the epilogue, measured
     // 1 % slower that way (each moment's accesses of the workgroup are spread
@@ -303,7 +313,15 @@ __device__ __forceinline__ void encrypt_item_split(const DevParams& p, const dou
         else return 2 * (tt + TS * i);
     };
     auto message_ntt = [&](const SplitLimb& sl, const LimbConst& lc, uint32_t l, const Packed8<RS>& elo,
-                           const Packed8<RS>& ehi, u64* dst, auto&& epi) {
+                           const Packed8<RS>& ehi, u64* dst, auto&& pre, auto&& epi) {
+        decltype(pre(0u)) pv[RS / 2];
+        auto fetch = [&](uint32_t base) {
+            return [&, base]() {
+                const uint32_t tt = opaque_tid(t);
+#pragma unroll
+                for (int i = 0; i < RS / 2; ++i) pv[i] = pre(base + pair_index(tt, i));
+            };
+        };
         const uint32_t tp0 = GS::tpart(0, opaque_tid(t));
         u64 u[RS];
 #pragma unroll
@@ -321,44 +339,52 @@ __device__ __forceinline__ void encrypt_item_split(const DevParams& p, const dou
             u[c] = sl.stage0(xl, xh, 0);
             dst[NH + k] = sl.stage0(xl, xh, 1);          // half-1 input, read back below
         }
-        sl.template run_half<WAVE>(0, [&](int c) { return u[c]; });
+        sl.template run_half<WAVE>(0, [&](int c) { return u[c]; }, fetch(0));
         {
             const uint32_t tt = opaque_tid(t);
 #pragma unroll
             for (int i = 0; i < RS / 2; ++i) {
                 const uint32_t k = pair_index(tt, i);
-                epi(k, sl.canon(k), sl.canon(k + 1));
+                epi(k, sl.canon(k), sl.canon(k + 1), pv[i]);
             }
         }
         const uint32_t tp1 = GS::tpart(0, opaque_tid(t));
-        sl.template run_half<WAVE>(1, [&](int c) { return dst[NH + jp(tp1, c)]; });
+        sl.template run_half<WAVE>(1, [&](int c) { return dst[NH + jp(tp1, c)]; }, fetch(NH));
         {
             const uint32_t tt = opaque_tid(t);
 #pragma unroll
             for (int i = 0; i < RS / 2; ++i) {
                 const uint32_t k = pair_index(tt, i);
-                epi(NH + k, sl.canon(k), sl.canon(k + 1));
+                epi(NH + k, sl.canon(k), sl.canon(k + 1), pv[i]);
             }
         }
     };
     // transform of a small-coefficient polynomial (samples), both halves; an
     // error polynomial (ERR true) is scaled by t under BGV
-    auto small_ntt = [&](const SplitLimb& sl, const LimbConst& lc, const Pair8& e, auto err, auto&& epi) {
+    auto small_ntt = [&](const SplitLimb& sl, const LimbConst& lc, const Pair8& e, auto err, auto&& pre,
+                         auto&& epi) {
         constexpr bool S = decltype(err)::value && BGV;
 #pragma unroll 1
         for (int h = 0; h < 2; ++h) {
             const Pair8 el = e.fresh();
+            decltype(pre(0u)) pv[RS / 2];
             sl.template run_half<WAVE>(h, [&](int c) {
                 return sl.stage0(sl.noise<S>(el.lo.get(c), p.noise_t, lc), sl.noise<S>(el.hi.get(c), p.noise_t, lc), h);
+            }, [&]() {
+                const uint32_t tt = opaque_tid(t);
+#pragma unroll
+                for (int i = 0; i < RS / 2; ++i) pv[i] = pre((uint32_t)h * NH + pair_index(tt, i));
             });
             const uint32_t tt = opaque_tid(t);
 #pragma unroll
             for (int i = 0; i < RS / 2; ++i) {
                 const uint32_t k = pair_index(tt, i);
-                epi((uint32_t)h * NH + k, sl.canon(k), sl.canon(k + 1));
+                epi((uint32_t)h * NH + k, sl.canon(k), sl.canon(k + 1), pv[i]);
             }
         }
     };
+
+    auto no_pre = [](uint32_t) { return 0; };     // vanilla: operands loaded in the epilogue
 
     if constexpr (SCHEME == ZINC_SCHEME_ZINC) {
         Pair8 e1, e2;
@@ -373,14 +399,14 @@ __device__ __forceinline__ void encrypt_item_split(const DevParams& p, const dou
             const u64* z1 = p.zero + (size_t)l * NF;
             const u64* z2 = p.zero + (size_t)(L + l) * NF;
             const Pair8 e1l = e1.fresh();
-            message_ntt(sl, lc, l, e1l.lo, e1l.hi, c1, [&](uint32_t k, u64 a, u64 b) {
-                const u64x2 z = load_pair(z1 + k);
-                store_pair_final(c1 + k, addmod(a, z.x, lc.q), addmod(b, z.y, lc.q));
-            });
-            small_ntt(sl, lc, e2, std::true_type{}, [&](uint32_t k, u64 a, u64 b) {
-                const u64x2 z = load_pair(z2 + k);
-                store_pair_final(c2 + k, addmod(a, z.x, lc.q), addmod(b, z.y, lc.q));
-            });
+            message_ntt(sl, lc, l, e1l.lo, e1l.hi, c1, [&](uint32_t k) { return load_pair(z1 + k); },
+                        [&](uint32_t k, u64 a, u64 b, u64x2 z) {
+                            store_pair_final(c1 + k, addmod(a, z.x, lc.q), addmod(b, z.y, lc.q));
+                        });
+            small_ntt(sl, lc, e2, std::true_type{}, [&](uint32_t k) { return load_pair(z2 + k); },
+                      [&](uint32_t k, u64 a, u64 b, u64x2 z) {
+                          store_pair_final(c2 + k, addmod(a, z.x, lc.q), addmod(b, z.y, lc.q));
+                      });
         }
     } else {
         Pair8 u, e1, e2;
@@ -398,14 +424,15 @@ __device__ __forceinline__ void encrypt_item_split(const DevParams& p, const dou
             const u64* pk1s = p.pk_sh + (size_t)l * NF;
             const u64* pk2 = p.pk + (size_t)(M + l) * NF;
             const u64* pk2s = p.pk_sh + (size_t)(M + l) * NF;
-            small_ntt(sl, lc, u, std::false_type{}, [&](uint32_t k, u64 a, u64 b) { store_pair(c2 + k, a, b); });   // u_hat
+            small_ntt(sl, lc, u, std::false_type{}, no_pre,
+                      [&](uint32_t k, u64 a, u64 b, int) { store_pair(c2 + k, a, b); });   // u_hat
             const Pair8 e1l = e1.fresh();
-            message_ntt(sl, lc, l, e1l.lo, e1l.hi, c1, [&](uint32_t k, u64 a, u64 b) {
+            message_ntt(sl, lc, l, e1l.lo, e1l.hi, c1, no_pre, [&](uint32_t k, u64 a, u64 b, int) {
                 const u64x2 u2 = load_pair(c2 + k), w = load_pair(pk1 + k), ws = load_pair(pk1s + k);
                 store_pair_final(c1 + k, addmod(a, sl.mul(u2.x, w.x, ws.x), lc.q),
                                  addmod(b, sl.mul(u2.y, w.y, ws.y), lc.q));
             });
-            small_ntt(sl, lc, e2, std::true_type{}, [&](uint32_t k, u64 a, u64 b) {
+            small_ntt(sl, lc, e2, std::true_type{}, no_pre, [&](uint32_t k, u64 a, u64 b, int) {
                 const u64x2 u2 = load_pair(c2 + k), w = load_pair(pk2 + k), ws = load_pair(pk2s + k);
                 store_pair_final(c2 + k, addmod(a, sl.mul(u2.x, w.x, ws.x), lc.q),
                                  addmod(b, sl.mul(u2.y, w.y, ws.y), lc.q));
